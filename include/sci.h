@@ -1,0 +1,187 @@
+/*
+ * sci.h — C ABI of the MI355X (gfx950) hot path of NNQS-SCI:
+ * exact coupled-configuration generation, on-device de-duplication, and the
+ * selected-space variational energy (arXiv 2604.15768).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Determinant ("key"): occupation bitstring over 2*n_orb spin orbitals packed
+ *   into W = ceil(2*n_orb/64) little-endian uint64 words.  Spin orbital
+ *   k = p + sigma*n_orb (sigma 0 = alpha, 1 = beta) is bit k&63 of word k>>6.
+ *   Keys compare as unsigned W*64-bit integers, word W-1 most significant.
+ *   An array of n keys is n*W contiguous uint64 ("[n][W]").
+ * Phase convention: |D> = a+_{k1} a+_{k2} ... |0> with k1 < k2 < ...; the
+ *   fermionic sign of an operator on spin orbital k is (-1)^(occupied spin
+ *   orbitals below k).
+ * Integrals: h1 is [n][n] (symmetric), eri is [n][n][n][n] in chemists'
+ *   notation (pq|rs), real and 8-fold symmetric.  Everything floating point is
+ *   IEEE double (FP64).
+ * Memory: "device" pointers are HIP device memory owned by the caller (the
+ *   library never frees or retains them past the enqueued work); "host"
+ *   pointers are ordinary host memory read before the call returns.
+ * Streams: every compute call enqueues on `stream` (a hipStream_t; NULL means
+ *   the null stream) and returns without synchronising.  Results, device
+ *   counters and device flags are valid once the stream has reached that point.
+ * Errors: each call returns a status (sci_status).  Argument errors that the
+ *   host can see are reported before anything is enqueued; the thread-local
+ *   text of the last error is available from sci_last_error().  Conditions
+ *   only the device can see set bits in *dev_flags (a caller-owned device
+ *   uint32 that the library only ORs into; the caller clears it).
+ */
+#ifndef SCI_H
+#define SCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sci_ham_s *sci_ham_t; /* opaque Hamiltonian handle */
+typedef void *sci_stream_t;          /* a hipStream_t */
+
+typedef enum {
+    SCI_OK = 0,
+    SCI_EINVAL = 1,       /* bad argument (null pointer, size, shape)        */
+    SCI_ECAPACITY = 2,    /* an output buffer is too small (host-visible)    */
+    SCI_ENOMEM = 3,       /* the library could not allocate its own tables   */
+    SCI_EHIP = 4,         /* a HIP runtime call failed                       */
+    SCI_EUNSUPPORTED = 5  /* size outside what this build supports           */
+} sci_status;
+
+/* bits of *dev_flags */
+#define SCI_FLAG_OVERFLOW 0x1u /* device-side count exceeded a capacity      */
+#define SCI_FLAG_BAD_DET 0x2u  /* a determinant has wrong popcounts / bits   */
+#define SCI_FLAG_UNSORTED 0x4u /* a set that must be strictly ascending isn't */
+
+/* Largest supported sizes of this build. */
+#define SCI_MAX_WORDS 2
+#define SCI_MAX_ORB 64
+
+/* Human-readable name of a status code (static string). */
+const char *sci_status_string(int32_t status);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *sci_last_error(void);
+
+/* W = ceil(2*n_orb/64). */
+int32_t sci_words(int32_t n_orb);
+
+/*
+ * Size of every coupled set C_i (paper Eq. 4: determinants reached by moving
+ * one or two occupied positions, spin conserving, D_i itself excluded):
+ *   n_a*v_a + n_b*v_b + C(n_a,2)C(v_a,2) + C(n_b,2)C(v_b,2) + n_a v_a n_b v_b,
+ * v = n_orb - n.  Returns -1 for invalid sizes.
+ */
+int64_t sci_n_coupled(int32_t n_orb, int32_t n_alpha, int32_t n_beta);
+
+/*
+ * Upload a Hamiltonian and build the device tables the kernels read
+ * (paper section 3.3, the single/double excitation tables; here the
+ * integral slices V_pq[a][b] = (ap|bq) and their antisymmetrised same-spin
+ * form).  h1_host, eri_host: host arrays as above.  On success *out owns
+ * about 2*n_orb^4*8 bytes of device memory until sci_ham_destroy.  The handle
+ * is immutable and may be used from several streams at once.  Synchronous.
+ * Errors: SCI_EINVAL (null pointers, n_alpha/n_beta outside [0, n_orb]),
+ * SCI_EUNSUPPORTED (n_orb > SCI_MAX_ORB), SCI_ENOMEM, SCI_EHIP.
+ */
+int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta,
+                       const double *h1_host, const double *eri_host, sci_ham_t *out);
+
+/* Free a handle (NULL is allowed).  The caller ensures no enqueued work still uses it. */
+int32_t sci_ham_destroy(sci_ham_t ham);
+
+/*
+ * Coupled-configuration generation (paper section 3.3, Algorithm 1; Eq. 4).
+ *
+ * Flat excitation index f = i*N_c + r for source i in [0, n_dets) and rank
+ * r in [0, N_c), N_c = sci_n_coupled(...).  Ranks follow a fixed order per
+ * source: alpha singles (p asc, a asc), beta singles, alpha-alpha doubles
+ * ((p<q) lexicographic, then (a<b) lexicographic), beta-beta doubles,
+ * alpha-beta doubles ((p, q, a, b) lexicographic), with p,q occupied and a,b
+ * empty in the source.  The call covers f in [exc_begin, exc_end).
+ *
+ * For each f: key = the determinant D' reached, hij = <D'|H|D_i> (FP64,
+ * Slater-Condon rules with the exact fermionic sign).
+ *
+ * dets      device [n_dets][W], each with n_alpha alpha and n_beta beta bits
+ *           and no bit at or above 2*n_orb (else SCI_FLAG_BAD_DET is set and
+ *           that source's outputs are zero).
+ * eps < 0   dense mode: entry f is written at index f - exc_begin of
+ *           out_keys ([capacity][W]) / out_hij ([capacity]); out_src (nullable)
+ *           receives i.  Requires capacity >= exc_end - exc_begin
+ *           (SCI_ECAPACITY otherwise).  Output is deterministic.
+ * eps >= 0  screened mode: only |hij| > eps is kept, compacted in an
+ *           unspecified order; out_src is required.  *n_out (device int64,
+ *           required here, nullable in dense mode) is set to the number kept;
+ *           if it exceeds capacity, SCI_FLAG_OVERFLOW is set and only the first
+ *           `capacity` slots are written.
+ * Errors: SCI_EINVAL (null handle/pointers, W mismatch, bad range),
+ *         SCI_ECAPACITY, SCI_EHIP.
+ */
+int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
+                        int64_t exc_begin, int64_t exc_end, double eps,
+                        uint64_t *out_keys, double *out_hij, int32_t *out_src,
+                        int64_t capacity, int64_t *n_out, uint32_t *dev_flags,
+                        sci_stream_t stream);
+
+/*
+ * Workspace bytes sci_dedup_merge needs for n_cand candidates of W words.
+ */
+size_t sci_dedup_workspace_bytes(int32_t n_words, int64_t n_cand);
+
+/*
+ * Global de-duplication and merge into a running set (paper section 3.2:
+ * sort, regular-sampling partition, local unique, merge).
+ *
+ * cand        device [n_cand][W], any order, duplicates allowed.
+ * set_in      device [*n_set_in][W], strictly ascending (the running set,
+ *             e.g. the selected space); n_set_in is a device int64.
+ * set_out     device [set_capacity][W]: receives sorted(set(cand) | set_in);
+ *             *n_set_out (device int64) its size.  Must not alias set_in or cand.
+ * novel       nullable device [novel_capacity][W]: sorted(set(cand) - set_in),
+ *             size in *n_novel (device int64; required when novel is given).
+ * workspace   device, at least sci_dedup_workspace_bytes(W, n_cand) bytes.
+ * If the union (or the novel set) does not fit, SCI_FLAG_OVERFLOW is set,
+ * the required size is still written to *n_set_out / *n_novel, and the
+ * contents of set_out / novel are unspecified; set_in is never modified.
+ * Errors: SCI_EINVAL, SCI_ECAPACITY (workspace too small), SCI_EHIP.
+ */
+int32_t sci_dedup_merge(int32_t n_words, const uint64_t *cand, int64_t n_cand,
+                        const uint64_t *set_in, const int64_t *n_set_in,
+                        uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
+                        uint64_t *novel, int64_t *n_novel, int64_t novel_capacity,
+                        void *workspace, size_t workspace_bytes,
+                        uint32_t *dev_flags, sci_stream_t stream);
+
+/*
+ * Workspace bytes sci_energy needs for n_sel determinants.
+ */
+size_t sci_energy_workspace_bytes(int64_t n_sel);
+
+/*
+ * Variational energy over the selected space (paper Eq. 1, with the sums of
+ * Eqs. 3 and 5 restricted to j in S), matrix-free:
+ *   (H psi)_i = H_ii psi_i + sum_{j in S, j != i} H_ij psi_j,
+ *   E = psi.(H psi) / psi.psi,   grad_i = dE/dpsi_i = 2((H psi)_i - E psi_i)/psi.psi.
+ * H_ij is recomputed from the integrals, never stored.
+ *
+ * sel      device [n_sel][W], strictly ascending (else SCI_FLAG_UNSORTED),
+ *          each with the handle's popcounts (else SCI_FLAG_BAD_DET).
+ * psi      device [n_sel] FP64 real amplitudes (not necessarily normalised).
+ * energy   device double [1] (required).
+ * h_psi    nullable device [n_sel]; grad nullable device [n_sel].
+ * workspace device, at least sci_energy_workspace_bytes(n_sel) bytes.
+ * The reduction order is fixed, so repeated calls give identical bits.
+ * Errors: SCI_EINVAL, SCI_ECAPACITY (workspace), SCI_EHIP.
+ */
+int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                   double *energy, double *h_psi, double *grad,
+                   void *workspace, size_t workspace_bytes,
+                   uint32_t *dev_flags, sci_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCI_H */

@@ -1,0 +1,270 @@
+"""Python binding of libsci (MI355X / gfx950 HIP kernels for the NNQS-SCI hot path).
+
+Argument marshalling only: every step of generation, de-duplication and
+energy runs in the HIP kernels of ``libsci.so``.  PyTorch supplies device
+memory (tensors; determinant keys are stored as int64 bit patterns) and the
+current HIP stream.  The functions mirror the C ABI of ``include/sci.h``:
+
+    sci_ham_create / sci_ham_destroy      -> Ham
+    sci_gen_coupled, sci_dedup_merge, sci_energy, sci_*_workspace_bytes,
+    sci_n_coupled, sci_words
+
+plus allocating conveniences (``gen_coupled``, ``dedup_merge``, ``energy``)
+that size outputs and check the device flags.  There is no fallback: if the
+library is not built, importing the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsci.so")
+
+SCI_OK, SCI_EINVAL, SCI_ECAPACITY, SCI_ENOMEM, SCI_EHIP, SCI_EUNSUPPORTED = range(6)
+FLAG_OVERFLOW, FLAG_BAD_DET, FLAG_UNSORTED = 0x1, 0x2, 0x4
+MAX_WORDS = 2
+MAX_ORB = 64
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsci.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i32, _i64, _f64, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+
+_lib.sci_status_string.argtypes = [_i32]
+_lib.sci_status_string.restype = ctypes.c_char_p
+_lib.sci_last_error.argtypes = []
+_lib.sci_last_error.restype = ctypes.c_char_p
+_lib.sci_words.argtypes = [_i32]
+_lib.sci_words.restype = _i32
+_lib.sci_n_coupled.argtypes = [_i32, _i32, _i32]
+_lib.sci_n_coupled.restype = _i64
+_lib.sci_ham_create.argtypes = [_i32, _i32, _i32, _P, _P, ctypes.POINTER(_P)]
+_lib.sci_ham_create.restype = _i32
+_lib.sci_ham_destroy.argtypes = [_P]
+_lib.sci_ham_destroy.restype = _i32
+_lib.sci_gen_coupled.argtypes = [_P, _P, _i64, _i64, _i64, _f64, _P, _P, _P, _i64, _P, _P, _P]
+_lib.sci_gen_coupled.restype = _i32
+_lib.sci_dedup_workspace_bytes.argtypes = [_i32, _i64]
+_lib.sci_dedup_workspace_bytes.restype = _sz
+_lib.sci_dedup_merge.argtypes = [_i32, _P, _i64, _P, _P, _P, _P, _i64, _P, _P, _i64, _P, _sz, _P, _P]
+_lib.sci_dedup_merge.restype = _i32
+_lib.sci_energy_workspace_bytes.argtypes = [_i64]
+_lib.sci_energy_workspace_bytes.restype = _sz
+_lib.sci_energy.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _P, _sz, _P, _P]
+_lib.sci_energy.restype = _i32
+
+
+class SciError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _lib.sci_last_error().decode()
+        super().__init__(f"{where}: {_lib.sci_status_string(status).decode()} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != SCI_OK:
+        raise SciError(status, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def sci_words(n_orb: int) -> int:
+    return int(_lib.sci_words(n_orb))
+
+
+def sci_n_coupled(n_orb: int, n_alpha: int, n_beta: int) -> int:
+    return int(_lib.sci_n_coupled(n_orb, n_alpha, n_beta))
+
+
+def sci_dedup_workspace_bytes(n_words: int, n_cand: int) -> int:
+    return int(_lib.sci_dedup_workspace_bytes(n_words, n_cand))
+
+
+def sci_energy_workspace_bytes(n_sel: int) -> int:
+    return int(_lib.sci_energy_workspace_bytes(n_sel))
+
+
+class Ham:
+    """Device Hamiltonian handle (sci_ham_create / sci_ham_destroy)."""
+
+    def __init__(self, n_orb, n_alpha, n_beta, h1, eri):
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        if h1.shape != (n_orb, n_orb) or eri.shape != (n_orb,) * 4:
+            raise ValueError("integral shapes do not match n_orb")
+        h = _P()
+        _check(_lib.sci_ham_create(n_orb, n_alpha, n_beta, h1.ctypes.data_as(_P), eri.ctypes.data_as(_P),
+                                   ctypes.byref(h)), "sci_ham_create")
+        self._h = h
+        self.n_orb, self.n_alpha, self.n_beta = n_orb, n_alpha, n_beta
+        self.W = sci_words(n_orb)
+        self.n_coupled = sci_n_coupled(n_orb, n_alpha, n_beta)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            _lib.sci_ham_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sci_ham_create(n_orb, n_alpha, n_beta, h1, eri) -> Ham:
+    return Ham(n_orb, n_alpha, n_beta, h1, eri)
+
+
+def sci_ham_destroy(ham: Ham) -> None:
+    ham.close()
+
+
+def sci_gen_coupled(ham: Ham, dets, n_dets, exc_begin, exc_end, eps, out_keys, out_hij, out_src,
+                    capacity, n_out, dev_flags, stream=None):
+    _check(_lib.sci_gen_coupled(ham.handle, _ptr(dets), n_dets, exc_begin, exc_end, float(eps),
+                                _ptr(out_keys), _ptr(out_hij), _ptr(out_src), capacity, _ptr(n_out),
+                                _ptr(dev_flags), _stream(stream)), "sci_gen_coupled")
+
+
+def sci_dedup_merge(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity,
+                    novel, n_novel, novel_capacity, workspace, workspace_bytes, dev_flags, stream=None):
+    _check(_lib.sci_dedup_merge(n_words, _ptr(cand), n_cand, _ptr(set_in), _ptr(n_set_in), _ptr(set_out),
+                                _ptr(n_set_out), set_capacity, _ptr(novel), _ptr(n_novel), novel_capacity,
+                                _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)),
+           "sci_dedup_merge")
+
+
+def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, workspace_bytes, dev_flags,
+               stream=None):
+    _check(_lib.sci_energy(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
+                           _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_energy")
+
+
+# ---------------------------------------------------------------------------
+# allocating conveniences
+# ---------------------------------------------------------------------------
+
+def keys_to_device(keys: np.ndarray, device="cuda") -> torch.Tensor:
+    """(n, W) uint64 numpy -> (n, W) int64 device tensor holding the same bits."""
+    a = np.ascontiguousarray(keys, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def keys_to_host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def new_flags(device="cuda") -> torch.Tensor:
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_flags(flags: torch.Tensor, where: str, allow=0):
+    v = int(flags.item()) & 0xFFFFFFFF
+    if v & ~allow:
+        names = [n for b, n in ((FLAG_OVERFLOW, "OVERFLOW"), (FLAG_BAD_DET, "BAD_DET"),
+                                (FLAG_UNSORTED, "UNSORTED")) if v & b]
+        raise RuntimeError(f"{where}: device flags {names}")
+    return v
+
+
+def gen_coupled(ham: Ham, dets: torch.Tensor, exc_begin=0, exc_end=None, eps=-1.0, with_src=False,
+                capacity=None, flags=None):
+    """Dense (eps<0) or screened coupled generation; returns (keys, hij, src, n_out tensor)."""
+    n = dets.shape[0]
+    if exc_end is None:
+        exc_end = n * ham.n_coupled
+    count = exc_end - exc_begin
+    if capacity is None:
+        capacity = count
+    dev = dets.device
+    keys = torch.empty((capacity, ham.W), dtype=torch.int64, device=dev)
+    hij = torch.empty(capacity, dtype=torch.float64, device=dev)
+    src = torch.empty(capacity, dtype=torch.int32, device=dev) if (with_src or eps >= 0) else None
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    own_flags = flags is None
+    if own_flags:
+        flags = new_flags(dev)
+    sci_gen_coupled(ham, dets, n, exc_begin, exc_end, eps, keys, hij, src, capacity, n_out, flags)
+    return keys, hij, src, n_out, flags
+
+
+def dedup_merge(cand: torch.Tensor, set_in: torch.Tensor, n_words: int, want_novel=False, set_capacity=None,
+                flags=None, workspace=None):
+    """sorted(set(cand) | set(set_in)) and optionally sorted(set(cand) - set(set_in)), on the device."""
+    dev = cand.device
+    n_cand = cand.shape[0]
+    n_set = set_in.shape[0]
+    if set_capacity is None:
+        set_capacity = n_cand + n_set
+    n_set_in = torch.tensor([n_set], dtype=torch.int64, device=dev)
+    set_out = torch.empty((max(set_capacity, 1), n_words), dtype=torch.int64, device=dev)
+    n_set_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    novel = torch.empty((max(n_cand, 1), n_words), dtype=torch.int64, device=dev) if want_novel else None
+    n_novel = torch.zeros(1, dtype=torch.int64, device=dev) if want_novel else None
+    ws_bytes = sci_dedup_workspace_bytes(n_words, n_cand)
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    sci_dedup_merge(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity,
+                    novel, n_novel, n_cand if want_novel else 0, workspace, workspace.numel(), flags)
+    return set_out, n_set_out, novel, n_novel, flags
+
+
+def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_grad=True, flags=None,
+           workspace=None):
+    dev = sel.device
+    n = sel.shape[0]
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    hp = torch.empty(n, dtype=torch.float64, device=dev) if want_hpsi else None
+    g = torch.empty(n, dtype=torch.float64, device=dev) if want_grad else None
+    ws_bytes = sci_energy_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    sci_energy(ham, sel, n, psi, e, hp, g, workspace, workspace.numel(), flags)
+    return e, hp, g, flags
+
+
+class SciEnergy(torch.autograd.Function):
+    """E(psi) = psi.H psi / psi.psi with the hand-written adjoint dE/dpsi = 2(H psi - E psi)/psi.psi.
+
+    Forward stores nothing but psi; backward recomputes H psi (H_ij never stored).
+    """
+
+    @staticmethod
+    def forward(ctx, psi, ham, sel):
+        e, _, _, flags = energy(ham, sel, psi.detach(), want_hpsi=False, want_grad=False)
+        ctx.ham = ham
+        ctx.save_for_backward(psi, sel)
+        return e[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        psi, sel = ctx.saved_tensors
+        _, _, g, _ = energy(ctx.ham, sel, psi.detach(), want_hpsi=False, want_grad=True)
+        return grad_out * g, None, None

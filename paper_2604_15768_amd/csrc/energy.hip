@@ -1,0 +1,308 @@
+// Selected-space variational energy (paper Eq. 1 with the sums of Eqs. 3/5
+// restricted to the selected set S), matrix-free, and its adjoint.
+//
+//   (H psi)_i = H_ii psi_i + sum_{j in S, j != i} H_ij psi_j
+//   E = psi.(H psi) / psi.psi,   g_i = 2((H psi)_i - E psi_i) / psi.psi
+//
+// Membership of j in C_i is decided by pair screening: H_ij can be non-zero
+// only when D_i XOR D_j has two or four set bits (at most two electrons moved,
+// paper section 2).  A workgroup owns 256 rows (one per lane) and streams every
+// determinant of S through LDS in tiles; all lanes read the same LDS entry at
+// a time (broadcast), so the screening is one XOR + popcount per pair.  For a
+// connected pair the lane rebuilds the excitation from the XOR bits and reads
+// the same integral tables the generation kernel uses; H_ij is never stored.
+// Row sums run in ascending j, block sums in a fixed tree, so repeated calls
+// are bit-identical.
+#include "sci_internal.hpp"
+
+namespace sci {
+
+constexpr int kRowThreads = 256;
+constexpr int kColTile = 1024;
+constexpr int kRedThreads = 256;
+
+struct EnergyArgs {
+    int n, na, nb;
+    const double *h1, *eri, *vdir, *vanti, *jmat, *kmat;
+    const uint64_t *sel;
+    int64_t n_sel;
+    const double *psi;
+    double *hpsi;      // [n_sel]
+    double *partial;   // [2][n_blocks]
+    double *scalars;   // [2]: numerator, denominator
+    double *energy;    // [1]
+    double *grad;      // nullable [n_sel]
+    uint32_t *flags;
+};
+
+template <int W>
+__device__ __forceinline__ int lowest_bit(const Key<W> &k) {
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (k.w[j]) return 64 * j + __ffsll((unsigned long long)k.w[j]) - 1;
+    return -1;
+}
+
+template <int W>
+__device__ __forceinline__ void clear_bit(Key<W> &k, int b) {
+    k.w[b >> 6] &= ~(1ull << (b & 63));
+}
+
+// <bra|H|ket> for bra = ket with one or two electrons moved (x = bra ^ ket, pc = popcount(x))
+template <int W>
+__device__ double offdiag_elem(const EnergyArgs &a, const Key<W> &bra, const Key<W> &ket, const Key<W> &x,
+                               int pc) {
+    const int n = a.n;
+    Key<W> holes, parts;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        holes.w[j] = ket.w[j] & x.w[j];
+        parts.w[j] = bra.w[j] & x.w[j];
+    }
+    // malformed input (unequal popcounts, bits at or above 2n, spin changes) contributes nothing;
+    // the caller flags such determinants
+    if (key_popc<W>(holes) * 2 != pc || key_popc<W>(parts) * 2 != pc) return 0.0;
+    if (pc == 2) {
+        const int P = lowest_bit<W>(holes), A = lowest_bit<W>(parts);
+        if (P >= 2 * n || A >= 2 * n || (P >= n) != (A >= n)) return 0.0;
+        const int sg = P >= n ? 1 : 0;
+        const int p = P - sg * n, t = A - sg * n;
+        const int par = key_popc_below<W>(ket, P) + key_popc_below<W>(ket, A) - (P < A ? 1 : 0);
+        double v = a.h1[t * n + p];
+        // occupied spin orbitals of the ket in ascending order (alpha block, then beta)
+        Key<W> occ = ket;
+        while (true) {
+            const int Q = lowest_bit<W>(occ);
+            if (Q < 0 || Q >= 2 * n) break;
+            clear_bit<W>(occ, Q);
+            if (Q == P) continue;
+            const int s2 = Q >= n ? 1 : 0;
+            const int q = Q - s2 * n;
+            const double jv = a.eri[((int64_t)(t * n + p) * n + q) * n + q];
+            const double kv = (s2 == sg) ? a.eri[((int64_t)(t * n + q) * n + q) * n + p] : 0.0;
+            v += jv - kv;
+        }
+        return (par & 1) ? -v : v;
+    }
+    // pc == 4: holes P<Q, particles A<B
+    const int P = lowest_bit<W>(holes);
+    clear_bit<W>(holes, P);
+    const int Q = lowest_bit<W>(holes);
+    const int A = lowest_bit<W>(parts);
+    clear_bit<W>(parts, A);
+    const int B = lowest_bit<W>(parts);
+    if (Q >= 2 * n || B >= 2 * n) return 0.0;
+    if ((P >= n) != (A >= n) || (Q >= n) != (B >= n)) return 0.0;  // spin of each pair conserved
+    const int par = key_popc_below<W>(ket, P) + key_popc_below<W>(ket, Q) - 1 + key_popc_below<W>(ket, B) -
+                    (P < B) - (Q < B) + key_popc_below<W>(ket, A) - (P < A) - (Q < A);
+    const int sp = P >= n, sq = Q >= n;
+    const int p = P - sp * n, q = Q - sq * n;
+    const int ta = A - (A >= n) * n, tb = B - (B >= n) * n;
+    const int64_t idx = ((int64_t)(p * n + q) * n + ta) * n + tb;
+    const double v = (sp == sq) ? a.vanti[idx] : a.vdir[idx];
+    return (par & 1) ? -v : v;
+}
+
+template <int W>
+__device__ double diag_elem(const EnergyArgs &a, const Key<W> &d) {
+    const int n = a.n;
+    double e1 = 0.0, e2 = 0.0;
+    Key<W> occ = d;
+    // ignore bits at or above 2n (such determinants are flagged by the caller)
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int lo = 64 * j;
+        if (2 * n <= lo) occ.w[j] = 0;
+        else if (2 * n < lo + 64) occ.w[j] &= (1ull << (2 * n - lo)) - 1ull;
+    }
+    while (true) {
+        const int P = lowest_bit<W>(occ);
+        if (P < 0) break;
+        clear_bit<W>(occ, P);
+        const int sp = P >= n, p = P - sp * n;
+        e1 += a.h1[p * n + p];
+        Key<W> rest = occ;  // spin orbitals above P
+        while (true) {
+            const int Q = lowest_bit<W>(rest);
+            if (Q < 0) break;
+            clear_bit<W>(rest, Q);
+            const int sq = Q >= n, q = Q - sq * n;
+            e2 += a.jmat[p * n + q] - ((sp == sq) ? a.kmat[p * n + q] : 0.0);
+        }
+    }
+    return e1 + e2;
+}
+
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
+    __shared__ Key<W> tile_keys[kColTile];
+    __shared__ double tile_psi[kColTile];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + tid;
+    const bool active = i < a.n_sel;
+    Key<W> di;
+#pragma unroll
+    for (int j = 0; j < W; ++j) di.w[j] = 0;
+    double acc = 0.0;
+    if (active) {
+        di = load_key<W>(a.sel, i);
+        int na, nb;
+        spin_popc<W>(di, a.n, na, nb);
+        if (na != a.na || nb != a.nb || key_popc<W>(di) != na + nb) atomicOr(a.flags, SCI_FLAG_BAD_DET);
+        if (i + 1 < a.n_sel && !key_less<W>(di, load_key<W>(a.sel, i + 1))) atomicOr(a.flags, SCI_FLAG_UNSORTED);
+    }
+    for (int64_t j0 = 0; j0 < a.n_sel; j0 += kColTile) {
+        const int cnt = (int)min<int64_t>(kColTile, a.n_sel - j0);
+        __syncthreads();
+        for (int t = tid; t < cnt; t += kRowThreads) {
+            tile_keys[t] = load_key<W>(a.sel, j0 + t);
+            tile_psi[t] = a.psi[j0 + t];
+        }
+        __syncthreads();
+        if (active) {
+            for (int t = 0; t < cnt; ++t) {
+                const Key<W> dj = tile_keys[t];
+                Key<W> x;
+#pragma unroll
+                for (int j = 0; j < W; ++j) x.w[j] = di.w[j] ^ dj.w[j];
+                const int pc = key_popc<W>(x);
+                if (pc == 2 || pc == 4) acc += offdiag_elem<W>(a, di, dj, x, pc) * tile_psi[t];
+            }
+        }
+    }
+    if (active) {
+        const double hii = diag_elem<W>(a, di);
+        a.hpsi[i] = hii * a.psi[i] + acc;
+    }
+}
+
+// per-block partial sums of psi_i*(H psi)_i and psi_i^2, fixed tree order
+__global__ __launch_bounds__(kRedThreads) void reduce_partial_kernel(EnergyArgs a) {
+    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    const int tid = threadIdx.x;
+    const int64_t per_block = (int64_t)kRedThreads * 8;
+    const int64_t base = (int64_t)blockIdx.x * per_block;
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t i = base + (int64_t)k * kRedThreads + tid;
+        if (i < a.n_sel) {
+            const double p = a.psi[i];
+            num += p * a.hpsi[i];
+            den += p * p;
+        }
+    }
+    s_num[tid] = num;
+    s_den[tid] = den;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            s_num[tid] += s_num[tid + s];
+            s_den[tid] += s_den[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.partial[2 * blockIdx.x] = s_num[0];
+        a.partial[2 * blockIdx.x + 1] = s_den[0];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(EnergyArgs a, int n_blocks) {
+    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    const int tid = threadIdx.x;
+    double num = 0.0, den = 0.0;
+    for (int b = tid; b < n_blocks; b += kRedThreads) {
+        num += a.partial[2 * b];
+        den += a.partial[2 * b + 1];
+    }
+    s_num[tid] = num;
+    s_den[tid] = den;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            s_num[tid] += s_num[tid + s];
+            s_den[tid] += s_den[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.scalars[0] = s_num[0];
+        a.scalars[1] = s_den[0];
+        a.energy[0] = s_num[0] / s_den[0];
+    }
+}
+
+__global__ void grad_kernel(EnergyArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_sel) return;
+    const double e = a.energy[0], den = a.scalars[1];
+    a.grad[i] = 2.0 * (a.hpsi[i] - e * a.psi[i]) / den;
+}
+
+static int64_t reduce_blocks(int64_t n_sel) { return std::max<int64_t>(1, ceil_div(n_sel, (int64_t)kRedThreads * 8)); }
+
+static size_t energy_ws(int64_t n_sel) {
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16);
+}
+
+}  // namespace sci
+
+using namespace sci;
+
+extern "C" size_t sci_energy_workspace_bytes(int64_t n_sel) {
+    if (n_sel < 0) return 0;
+    return energy_ws(n_sel);
+}
+
+extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                              double *energy, double *h_psi, double *grad, void *workspace,
+                              size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
+    set_error("");
+    if (!ham) return fail(SCI_EINVAL, "sci_energy: NULL handle");
+    if (n_sel < 1) return fail(SCI_EINVAL, "sci_energy: n_sel must be >= 1");
+    if (!sel || !psi || !energy || !dev_flags || !workspace)
+        return fail(SCI_EINVAL, "sci_energy: NULL pointer argument");
+    if (workspace_bytes < energy_ws(n_sel))
+        return fail(SCI_ECAPACITY, "sci_energy: workspace %zu < %zu bytes", workspace_bytes, energy_ws(n_sel));
+    const HamDev &d = ham->dev;
+    if (d.W > SCI_MAX_WORDS) return fail(SCI_EUNSUPPORTED, "sci_energy: W=%d", d.W);
+    hipStream_t st = (hipStream_t)stream;
+
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    char *ws = (char *)workspace;
+    EnergyArgs a;
+    a.n = d.n_orb;
+    a.na = d.n_alpha;
+    a.nb = d.n_beta;
+    a.h1 = d.h1;
+    a.eri = d.eri;
+    a.vdir = d.vdir;
+    a.vanti = d.vanti;
+    a.jmat = d.jmat;
+    a.kmat = d.kmat;
+    a.sel = sel;
+    a.n_sel = n_sel;
+    a.psi = psi;
+    a.hpsi = h_psi ? h_psi : (double *)ws;
+    a.partial = (double *)(ws + al((size_t)n_sel * 8));
+    a.scalars = (double *)(ws + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16));
+    a.energy = energy;
+    a.grad = grad;
+    a.flags = dev_flags;
+
+    const int64_t row_blocks = ceil_div(n_sel, kRowThreads);
+    if (d.W == 1) hipLaunchKernelGGL(hpsi_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
+    else hipLaunchKernelGGL(hpsi_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
+    SCI_HIP_TRY(hipGetLastError());
+    const int64_t nb = reduce_blocks(n_sel);
+    hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);
+    SCI_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, st, a, (int)nb);
+    SCI_HIP_TRY(hipGetLastError());
+    if (grad) {
+        hipLaunchKernelGGL(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
+        SCI_HIP_TRY(hipGetLastError());
+    }
+    return SCI_OK;
+}

@@ -1,0 +1,310 @@
+"""GPU parity: HIP path (through the C ABI binding) vs the CPU oracle.
+
+Bar: keys, sources and sets bit-exact; H_ij within 1e-12 Ha; E within 1e-10 Ha;
+gradient within 1e-10 per component.
+"""
+import numpy as np
+import pytest
+import torch  # imported at collection: the first import on a fresh box is slow
+
+import oracle
+import sci_inputs as si
+from tests.gpu_common import E_TOL, G_TOL, H_TOL, ham, pick_sources, require_gpu, say, system
+
+pytestmark = pytest.mark.gpu
+
+
+def _gen(sci, h, dets_np, **kw):
+    import torch
+    d = sci.keys_to_device(dets_np)
+    keys, hij, src, n_out, flags = sci.gen_coupled(h, d, **kw)
+    torch.cuda.synchronize()
+    return keys, hij, src, n_out, flags
+
+
+# ---------------------------------------------------------------------------
+# generation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,n_src", [("tiny", None), ("medium", 48), ("large", 12)])
+def test_gen_dense_matches_oracle(name, n_src):
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    dets = s.dets if n_src is None else s.dets[pick_sources(s.dets.shape[0], n_src, 7)]
+    say(f"gen dense {name}: {dets.shape[0]} sources x {h.n_coupled}")
+    keys, hij, src, n_out, flags = _gen(sci, h, dets, with_src=True)
+    assert sci.check_flags(flags, "gen") == 0
+    assert int(n_out.item()) == dets.shape[0] * h.n_coupled
+    ok, oh, osrc = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
+    gk = sci.keys_to_host(keys)
+    assert np.array_equal(gk, ok), "coupled determinants differ"
+    assert np.array_equal(src.cpu().numpy(), osrc)
+    gh = hij.cpu().numpy()
+    err = np.max(np.abs(gh - oh))
+    say(f"  max |dH| = {err:.3e}, exact fraction = {np.mean(gh == oh):.4f}")
+    assert err <= H_TOL
+    # signs are exact: any sign flip shows as |dH| = 2|H|
+    assert np.all(np.sign(gh[np.abs(oh) > 1e-9]) == np.sign(oh[np.abs(oh) > 1e-9]))
+
+
+def test_gen_chunked_ranges_equal_full():
+    """Arbitrary [exc_begin, exc_end) windows, across source boundaries, equal the full output."""
+    sci = require_gpu()
+    s = system("medium")
+    h = ham("medium")
+    dets = s.dets[:7]
+    full_k, full_h, _, _, _ = _gen(sci, h, dets)
+    total = 7 * h.n_coupled
+    rng = np.random.Generator(np.random.PCG64(3))
+    cuts = sorted(set([0, total, 1, total - 1, h.n_coupled, 2 * h.n_coupled + 5] +
+                      rng.integers(0, total, 6).tolist()))
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        k, hh, _, n_out, flags = _gen(sci, h, dets, exc_begin=a, exc_end=b)
+        assert int(n_out.item()) == b - a
+        assert np.array_equal(sci.keys_to_host(k), sci.keys_to_host(full_k[a:b]))
+        assert np.array_equal(hh.cpu().numpy(), full_h[a:b].cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_gen_screened_matches_oracle(name):
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    dets = s.dets if name == "tiny" else s.dets[pick_sources(s.dets.shape[0], 16, 9)]
+    ok, oh, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
+    eps = float(np.quantile(np.abs(oh), 0.87))
+    say(f"gen screened {name}: eps={eps:.4e}")
+    keys, hij, src, n_out, flags = _gen(sci, h, dets, eps=eps)
+    assert sci.check_flags(flags, "gen") == 0
+    n = int(n_out.item())
+    nc = h.n_coupled
+    osrc = np.repeat(np.arange(dets.shape[0]), nc)
+    keep = np.abs(oh) > eps
+    border = np.abs(np.abs(oh) - eps) < 1e-12
+    want = {(int(a), *map(int, k)) for a, k, kp, b in zip(osrc, ok, keep, border) if kp and not b}
+    gk = sci.keys_to_host(keys[:n])
+    got = {(int(a), *map(int, k)) for a, k in zip(src[:n].cpu().numpy(), gk)}
+    got_all = got
+    bset = {(int(a), *map(int, k)) for a, k, b in zip(osrc, ok, border) if b}
+    assert want == got_all - bset
+    assert n == len(got)
+    # overflow: capacity below the kept count sets the flag and still reports the count
+    keys2, _, _, n2, flags2 = _gen(sci, h, dets, eps=eps, capacity=max(1, n // 2))
+    assert int(n2.item()) == n
+    assert sci.check_flags(flags2, "gen", allow=sci.FLAG_OVERFLOW) & sci.FLAG_OVERFLOW
+
+
+def test_gen_bad_determinant_flag():
+    sci = require_gpu()
+    s = system("tiny")
+    h = ham("tiny")
+    bad = s.dets[:3].copy()
+    bad[1, 0] ^= np.uint64(1) << np.uint64(2 * s.n_orb + 1)  # a bit beyond 2*n_orb
+    keys, hij, _, _, flags = _gen(sci, h, bad)
+    assert sci.check_flags(flags, "gen", allow=sci.FLAG_BAD_DET) & sci.FLAG_BAD_DET
+    nc = h.n_coupled
+    ok, oh, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, s.dets[:1])
+    assert np.array_equal(sci.keys_to_host(keys[:nc]), ok)
+    assert np.all(hij[nc:2 * nc].cpu().numpy() == 0.0)
+
+
+def test_gen_empty_range():
+    sci = require_gpu()
+    s = system("tiny")
+    h = ham("tiny")
+    keys, hij, _, n_out, flags = _gen(sci, h, s.dets[:2], exc_begin=5, exc_end=5)
+    assert int(n_out.item()) == 0 and keys.shape[0] == 0
+
+
+@pytest.mark.parametrize("n,na,nb", [(5, 1, 1), (6, 3, 0), (33, 2, 3), (40, 20, 19), (64, 3, 4)])
+def test_gen_edge_shapes(n, na, nb):
+    """Edge shapes: one electron per spin, an empty spin, W=2 boundary, half filling, n_orb=64."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(n + 100 * na + nb))
+    h1 = si.make_h1(rng, n)
+    eri = si.make_eri(rng, n, 6)
+    W = si.n_words(n)
+    picks = set()
+    while len(picks) < 6:
+        picks.add(si.pack_int(rng.choice(n, na, replace=False), rng.choice(n, nb, replace=False), n))
+    dets = si.sort_keys(si.ints_to_words(sorted(picks), W))
+    say(f"gen edge n={n} na={na} nb={nb}")
+    h = sci.Ham(n, na, nb, h1, eri)
+    keys, hij, _, _, flags = _gen(sci, h, dets)
+    assert sci.check_flags(flags, "gen") == 0
+    ok, oh, _ = oracle.gen_coupled(n, na, nb, h1, eri, dets)
+    assert np.array_equal(sci.keys_to_host(keys), ok)
+    assert np.max(np.abs(hij.cpu().numpy() - oh), initial=0.0) <= H_TOL
+
+
+# ---------------------------------------------------------------------------
+# de-duplication
+# ---------------------------------------------------------------------------
+
+def _dedup_check(sci, cand_np, set_np, W, want_novel=True):
+    import torch
+    cand = sci.keys_to_device(cand_np) if cand_np.shape[0] else torch.empty((0, W), dtype=torch.int64, device="cuda")
+    setin = sci.keys_to_device(set_np) if set_np.shape[0] else torch.empty((0, W), dtype=torch.int64, device="cuda")
+    out, n_out, nov, n_nov, flags = sci.dedup_merge(cand, setin, W, want_novel=want_novel)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "dedup") == 0
+    ou, onov = oracle.dedup_merge(W, cand_np, set_np)
+    n = int(n_out.item())
+    assert n == ou.shape[0], f"|union| {n} != {ou.shape[0]}"
+    assert np.array_equal(sci.keys_to_host(out[:n]), ou)
+    if want_novel:
+        m = int(n_nov.item())
+        assert m == onov.shape[0]
+        assert np.array_equal(sci.keys_to_host(nov[:m]), onov)
+
+
+def _random_keys(rng, n, W, pool=None, top=True):
+    if pool is None:
+        pool = max(1, n // 3)
+    base = rng.integers(0, 2**63, size=(pool, W), dtype=np.int64).astype(np.uint64)
+    if top:
+        base[: pool // 2, -1] |= np.uint64(1) << np.uint64(63)
+    return base[rng.integers(0, pool, n)]
+
+
+@pytest.mark.parametrize("W", [1, 2])
+@pytest.mark.parametrize("n", [0, 1, 100, 2047, 2048, 2049, 4096, 4097, 50_000, 1_200_000])
+def test_dedup_random_matches_oracle(W, n):
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(n * 7 + W))
+    say(f"dedup random W={W} n={n}")
+    cand = _random_keys(rng, n, W)
+    setin = si.sort_keys(np.unique(_random_keys(rng, 300, W, pool=600), axis=0)) if n % 2 == 0 else \
+        np.zeros((0, W), np.uint64)
+    if setin.shape[0] and n:
+        setin = si.sort_keys(np.concatenate([setin, cand[:5]]))
+        setin = setin[np.concatenate([[True], np.any(setin[1:] != setin[:-1], axis=1)])]
+    _dedup_check(sci, cand, setin, W)
+
+
+@pytest.mark.parametrize("W", [1, 2])
+def test_dedup_heavy_hitters(W):
+    """A few keys repeated far beyond one LDS bucket (oversized-bucket path)."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(40 + W))
+    few = _random_keys(rng, 5, W, pool=5)
+    many = _random_keys(rng, 20_000, W, pool=20_000)
+    cand = np.concatenate([np.repeat(few, 60_000, axis=0), many])
+    cand = cand[rng.permutation(cand.shape[0])]
+    say(f"dedup heavy W={W} n={cand.shape[0]}")
+    _dedup_check(sci, cand, np.zeros((0, W), np.uint64), W)
+    # everything equal
+    _dedup_check(sci, np.repeat(few[:1], 300_000, axis=0), few[1:2][np.argsort([0])], W)
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_dedup_of_generated_candidates(name):
+    """Skewed real keys: coupled sets of a selected-set slice merged into the selected set."""
+    import torch
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    dets = s.dets if name == "tiny" else s.dets[:2000]
+    keys, _, _, _, _ = _gen(sci, h, dets)
+    cand_np = sci.keys_to_host(keys)
+    say(f"dedup generated {name}: {cand_np.shape[0]} candidates")
+    _dedup_check(sci, cand_np, s.dets, s.W)
+
+
+def test_dedup_flags():
+    import torch
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(5))
+    cand = _random_keys(rng, 10_000, 1)
+    c = sci.keys_to_device(cand)
+    empty = torch.empty((0, 1), dtype=torch.int64, device="cuda")
+    out, n_out, _, _, flags = sci.dedup_merge(c, empty, 1, set_capacity=10)
+    torch.cuda.synchronize()
+    ou, _ = oracle.dedup_merge(1, cand)
+    assert int(n_out.item()) == ou.shape[0]
+    assert sci.check_flags(flags, "dedup", allow=sci.FLAG_OVERFLOW) & sci.FLAG_OVERFLOW
+    unsorted = sci.keys_to_device(np.array([[5], [3], [9]], dtype=np.uint64))
+    _, _, _, _, flags2 = sci.dedup_merge(c, unsorted, 1)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags2, "dedup", allow=sci.FLAG_UNSORTED) & sci.FLAG_UNSORTED
+
+
+# ---------------------------------------------------------------------------
+# energy
+# ---------------------------------------------------------------------------
+
+def test_energy_tiny_matches_oracle():
+    import torch
+    sci = require_gpu()
+    s = system("tiny")
+    h = ham("tiny")
+    sel = sci.keys_to_device(s.dets)
+    psi = torch.from_numpy(s.psi).cuda()
+    e, hp, g, flags = sci.energy(h, sel, psi)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy") == 0
+    oe, ohp, og = oracle.energy(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, s.dets, s.psi)
+    say(f"energy tiny: gpu {e.item():.15f} oracle {oe:.15f}")
+    assert abs(e.item() - oe) <= E_TOL
+    assert np.max(np.abs(hp.cpu().numpy() - ohp)) <= H_TOL * 10
+    assert np.max(np.abs(g.cpu().numpy() - og)) <= G_TOL
+    # bit-reproducible
+    e2, hp2, g2, _ = sci.energy(h, sel, psi)
+    torch.cuda.synchronize()
+    assert e2.item() == e.item() and torch.equal(hp2, hp) and torch.equal(g2, g)
+
+
+def test_energy_full_space_eigenvector():
+    import torch
+    sci = require_gpu()
+    n, na, nb = 6, 3, 2
+    rng = np.random.Generator(np.random.PCG64(12))
+    h1 = si.make_h1(rng, n)
+    eri = si.make_eri(rng, n, 8)
+    basis = si.all_determinants(n, na, nb)
+    hd = oracle.dense_h_sc(n, na, nb, h1, eri, basis)
+    w, v = np.linalg.eigh(hd)
+    h = sci.Ham(n, na, nb, h1, eri)
+    e, hp, g, flags = sci.energy(h, sci.keys_to_device(basis), torch.from_numpy(v[:, 0].copy()).cuda())
+    torch.cuda.synchronize()
+    assert abs(e.item() - w[0]) <= E_TOL
+    assert np.max(np.abs(g.cpu().numpy())) <= 1e-9
+
+
+@pytest.mark.parametrize("name,n_rows", [("medium", 24), ("large", 8)])
+def test_energy_sampled_rows(name, n_rows):
+    import torch
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    sel = sci.keys_to_device(s.dets)
+    psi = torch.from_numpy(s.psi).cuda()
+    say(f"energy {name}: n_sel={s.dets.shape[0]}")
+    e, hp, g, flags = sci.energy(h, sel, psi)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy") == 0
+    rows = pick_sources(s.dets.shape[0], n_rows, 21)
+    ohp = oracle.hpsi_rows(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, s.dets, s.psi, rows)
+    ghp = hp.cpu().numpy()
+    err = np.max(np.abs(ghp[rows] - ohp))
+    say(f"  sampled rows max |d(H psi)| = {err:.3e}")
+    assert err <= 1e-11
+    # properties at full size: E = psi.Hpsi/psi.psi, g = 2(Hpsi - E psi)/psi.psi, psi.g = 0
+    num = float(np.dot(s.psi, ghp))
+    den = float(np.dot(s.psi, s.psi))
+    assert abs(e.item() - num / den) <= E_TOL
+    gg = g.cpu().numpy()
+    assert np.max(np.abs(gg - 2 * (ghp - e.item() * s.psi) / den)) <= G_TOL
+    assert abs(float(np.dot(s.psi, gg))) <= 1e-9
+
+
+def test_energy_flags():
+    import torch
+    sci = require_gpu()
+    s = system("tiny")
+    h = ham("tiny")
+    sel = sci.keys_to_device(s.dets[::-1].copy())
+    _, _, _, flags = sci.energy(h, sel, torch.from_numpy(s.psi).cuda())
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy", allow=sci.FLAG_UNSORTED) & sci.FLAG_UNSORTED
