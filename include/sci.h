@@ -180,6 +180,18 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
                    void *workspace, size_t workspace_bytes,
                    uint32_t *dev_flags, sci_stream_t stream);
 
+/*
+ * Per-kernel timing, for profiling and roofline reports (not part of the
+ * method).  While enabled (process-wide), every kernel the library launches
+ * is bracketed by two HIP events recorded on that kernel's stream.
+ * sci_profile_read waits for the recorded events, copies up to `cap`
+ * (static kernel name, milliseconds) pairs in launch order into names/ms,
+ * clears the record and returns the number of records that were held (which
+ * may exceed cap).  Returns -1 on a HIP error.  Synchronous.
+ */
+int32_t sci_profile_enable(int32_t on);
+int32_t sci_profile_read(const char **names, float *ms, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,10 @@ _lib.sci_energy_workspace_bytes.argtypes = [_i64]
 _lib.sci_energy_workspace_bytes.restype = _sz
 _lib.sci_energy.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _P, _sz, _P, _P]
 _lib.sci_energy.restype = _i32
+_lib.sci_profile_enable.argtypes = [_i32]
+_lib.sci_profile_enable.restype = _i32
+_lib.sci_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), _i32]
+_lib.sci_profile_read.restype = _i32
 
 
 class SciError(RuntimeError):
@@ -99,6 +103,20 @@ def sci_dedup_workspace_bytes(n_words: int, n_cand: int) -> int:
 
 def sci_energy_workspace_bytes(n_sel: int) -> int:
     return int(_lib.sci_energy_workspace_bytes(n_sel))
+
+
+def sci_profile_enable(on: bool) -> None:
+    _lib.sci_profile_enable(1 if on else 0)
+
+
+def sci_profile_read(cap: int = 4096):
+    """[(kernel name, ms), ...] of the launches recorded since the last read."""
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_float * cap)()
+    n = _lib.sci_profile_read(names, ms, cap)
+    if n < 0:
+        raise SciError(SCI_EHIP, "sci_profile_read")
+    return [(names[i].decode(), float(ms[i])) for i in range(min(n, cap))]
 
 
 class Ham:

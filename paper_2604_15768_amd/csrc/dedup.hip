@@ -828,10 +828,10 @@ static WsLayout ws_layout(int64_t n) {
 static hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_t *sums, int64_t *total_out,
                               hipStream_t st) {
     const int64_t nb = std::max<int64_t>(1, ceil_div(n_bound, kScanPer));
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, (const int64_t *)x, n_dev,
+    SCI_LAUNCH(scan_reduce_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, (const int64_t *)x, n_dev,
                        n_bound, sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kDThreads), 0, st, sums, nb, total_out);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, x, n_dev, n_bound,
+    SCI_LAUNCH(scan_sums_kernel, dim3(1), dim3(kDThreads), 0, st, sums, nb, total_out);
+    SCI_LAUNCH(scan_apply_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, x, n_dev, n_bound,
                        (const int64_t *)sums);
     return hipGetLastError();
 }
@@ -865,7 +865,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
         const uint64_t *cur = cand;
         const int64_t *seg_cur = segA;
         int S_cur = 1;
-        hipLaunchKernelGGL(init_level0_kernel, dim3(1), dim3(64), 0, st, segA, n);
+        SCI_LAUNCH(init_level0_kernel, dim3(1), dim3(64), 0, st, segA, n);
         uint64_t *sort_src;
         const int64_t *final_seg;
         int64_t n_final;
@@ -903,24 +903,24 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
                 a.sample_buf = (uint64_t *)(ws + L.samples);
                 const int64_t tiles_bound = ceil_div(n, a.tile) + S_cur;
                 a.max_tiles = tiles_bound;
-                hipLaunchKernelGGL(splitter_kernel<W>, dim3(S_cur), dim3(kDThreads), 0, st, a);
-                hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH(splitter_kernel<W>, dim3(S_cur), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
                 if (lvl == 0) {
-                    hipLaunchKernelGGL((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                    SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
                 } else {
-                    hipLaunchKernelGGL((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                    SCI_LAUNCH((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
                 }
                 SCI_HIP_TRY(hipGetLastError());
                 // exclusive scan of all counters -> absolute output offsets
                 const int64_t cbound = tiles_bound * (int64_t)a.F;
                 SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 1, st));
                 if (lvl == 0) {
-                    hipLaunchKernelGGL((scatter_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                    SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
                 } else {
-                    hipLaunchKernelGGL((scatter_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                    SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
                 }
                 const int64_t slots = (int64_t)S_cur * a.F;
-                hipLaunchKernelGGL(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
+                SCI_LAUNCH(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
                 SCI_HIP_TRY(hipGetLastError());
                 cur = a.out;
                 seg_cur = a.seg_out;
@@ -931,13 +931,13 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             n_final = S_cur;
         }
         // sorted unique runs per final bucket, written into bufA at the bucket offsets
-        hipLaunchKernelGGL(bucket_sort_unique_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
+        SCI_LAUNCH(bucket_sort_unique_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
                            (const uint64_t *)sort_src, bufA, bufB, final_seg, ucount);
         SCI_HIP_TRY(hipGetLastError());
         SCI_HIP_TRY(launch_set_i64(ucount + n_final, 0, st));
         SCI_HIP_TRY(device_scan(ucount, nullptr, n_final + 1, sums, nrun, st));
         uint64_t *dest = bufB;  // free once the buckets are sorted
-        hipLaunchKernelGGL(compact_runs_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
+        SCI_LAUNCH(compact_runs_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
                            (const uint64_t *)bufA, final_seg, (const int64_t *)ucount, dest);
         SCI_HIP_TRY(hipGetLastError());
         run = dest;
@@ -948,7 +948,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
 
     // merge the run into the set
     if (set_in && n_set_in)
-        hipLaunchKernelGGL(check_sorted_kernel<W>, dim3(1024), dim3(256), 0, st, set_in, n_set_in, flags);
+        SCI_LAUNCH(check_sorted_kernel<W>, dim3(1024), dim3(256), 0, st, set_in, n_set_in, flags);
     MergeArgs m{};
     m.A = run;
     m.nA = nrun;
@@ -962,9 +962,9 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     m.novel_cap = novel_cap;
     m.blk = (int64_t *)(ws + L.blk);
     m.flags = flags;
-    hipLaunchKernelGGL((merge_kernel<W, 0>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
-    hipLaunchKernelGGL(merge_scan_kernel, dim3(1), dim3(kDThreads), 0, st, m);
-    hipLaunchKernelGGL((merge_kernel<W, 1>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
+    SCI_LAUNCH((merge_kernel<W, 0>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
+    SCI_LAUNCH(merge_scan_kernel, dim3(1), dim3(kDThreads), 0, st, m);
+    SCI_LAUNCH((merge_kernel<W, 1>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
     SCI_HIP_TRY(hipGetLastError());
     return SCI_OK;
 }

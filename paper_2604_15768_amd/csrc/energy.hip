@@ -292,16 +292,16 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
     a.flags = dev_flags;
 
     const int64_t row_blocks = ceil_div(n_sel, kRowThreads);
-    if (d.W == 1) hipLaunchKernelGGL(hpsi_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
-    else hipLaunchKernelGGL(hpsi_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
+    if (d.W == 1) SCI_LAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
+    else SCI_LAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
     SCI_HIP_TRY(hipGetLastError());
     const int64_t nb = reduce_blocks(n_sel);
-    hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);
+    SCI_LAUNCH(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);
     SCI_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, st, a, (int)nb);
+    SCI_LAUNCH(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, st, a, (int)nb);
     SCI_HIP_TRY(hipGetLastError());
     if (grad) {
-        hipLaunchKernelGGL(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
+        SCI_LAUNCH(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
         SCI_HIP_TRY(hipGetLastError());
     }
     return SCI_OK;

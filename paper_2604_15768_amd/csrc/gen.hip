@@ -312,11 +312,11 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
     if (grid > 0x7fffffffll) return fail(SCI_EUNSUPPORTED, "sci_gen_coupled: range too large for one launch");
     dim3 g((unsigned)grid), b(kGenThreads);
     if (d.W == 1) {
-        if (dense) hipLaunchKernelGGL((gen_kernel<1, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((gen_kernel<1, false>), g, b, 0, st, a);
+        if (dense) SCI_LAUNCH((gen_kernel<1, true>), g, b, 0, st, a);
+        else SCI_LAUNCH((gen_kernel<1, false>), g, b, 0, st, a);
     } else {
-        if (dense) hipLaunchKernelGGL((gen_kernel<2, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((gen_kernel<2, false>), g, b, 0, st, a);
+        if (dense) SCI_LAUNCH((gen_kernel<2, true>), g, b, 0, st, a);
+        else SCI_LAUNCH((gen_kernel<2, false>), g, b, 0, st, a);
     }
     SCI_HIP_TRY(hipGetLastError());
     return SCI_OK;

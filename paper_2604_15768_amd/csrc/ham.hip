@@ -3,7 +3,9 @@
 // pre-arranged per source/target orbitals so a kernel reads one entry per
 // excitation).  Also the ABI's error plumbing and size helpers.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -54,6 +56,46 @@ __global__ void build_tables_kernel(const double *__restrict__ eri, double *__re
     }
 }
 
+// ---------------------------------------------------------------------------
+// per-launch timing
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::atomic<int> g_prof_on{0};
+std::vector<ProfRec> g_prof;      // records of the current window
+std::vector<hipEvent_t> g_events; // pool of created events
+size_t g_next_event = 0;
+
+hipEvent_t take_event() {
+    if (g_next_event == g_events.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_events.push_back(e);
+    }
+    return g_events[g_next_event++];
+}
+}  // namespace
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : st(s), slot(-1) {
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r{name, take_event(), take_event()};
+    if (!r.a || !r.b) return;
+    if (hipEventRecord(r.a, st) != hipSuccess) return;
+    slot = (int)g_prof.size();
+    g_prof.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    (void)hipEventRecord(g_prof[slot].b, st);
+}
+
 __global__ void set_i64_kernel(int64_t *p, int64_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -63,12 +105,12 @@ __global__ void set_u32_kernel(uint32_t *p, uint32_t v) {
 }
 
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st) {
-    hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, st, p, v);
+    SCI_LAUNCH(set_i64_kernel, dim3(1), dim3(64), 0, st, p, v);
     return hipGetLastError();
 }
 
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t st) {
-    hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, p, v);
+    SCI_LAUNCH(set_u32_kernel, dim3(1), dim3(64), 0, st, p, v);
     return hipGetLastError();
 }
 
@@ -157,7 +199,7 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
 
     const int threads = 256;
     const int64_t blocks = ceil_div(n4, threads);
-    hipLaunchKernelGGL(build_tables_kernel, dim3((unsigned)blocks), dim3(threads), 0, 0,
+    SCI_LAUNCH(build_tables_kernel, dim3((unsigned)blocks), dim3(threads), 0, 0,
                        (const double *)(base + off_eri), (double *)(base + off_vdir),
                        (double *)(base + off_vanti), (double *)(base + off_j),
                        (double *)(base + off_k), (int)n);
@@ -188,6 +230,30 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
     h->block = block;
     *out = h;
     return SCI_OK;
+}
+
+int32_t sci_profile_enable(int32_t on) {
+    g_prof_on.store(on ? 1 : 0);
+    return SCI_OK;
+}
+
+int32_t sci_profile_read(const char **names, float *ms, int32_t cap) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    const int32_t n = (int32_t)g_prof.size();
+    int32_t rc = n;
+    for (int32_t i = 0; i < n; ++i) {
+        float t = 0.0f;
+        if (hipEventSynchronize(g_prof[i].b) != hipSuccess ||
+            hipEventElapsedTime(&t, g_prof[i].a, g_prof[i].b) != hipSuccess)
+            rc = -1;
+        if (i < cap) {
+            if (names) names[i] = g_prof[i].name;
+            if (ms) ms[i] = t;
+        }
+    }
+    g_prof.clear();
+    g_next_event = 0;
+    return rc;
 }
 
 int32_t sci_ham_destroy(sci_ham_t ham) {

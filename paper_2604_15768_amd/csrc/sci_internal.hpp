@@ -49,6 +49,21 @@ namespace sci {
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st);
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t st);
 
+// optional per-launch timing (sci_profile_enable): events around each launch
+struct ProfScope {
+    ProfScope(const char *name, hipStream_t st);
+    ~ProfScope();
+    hipStream_t st;
+    int slot;
+};
+
+// every kernel launch of the library goes through this (timing when enabled)
+#define SCI_LAUNCH(kern, grid, block, shm, st, ...)                 \
+    do {                                                            \
+        ::sci::ProfScope sci_prof_scope_(#kern, (st));              \
+        hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__); \
+    } while (0)
+
 // thread-local last-error text
 void set_error(const char *fmt, ...);
 int32_t fail(int32_t status, const char *fmt, ...);
