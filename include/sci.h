@@ -77,7 +77,7 @@ int64_t sci_n_coupled(int32_t n_orb, int32_t n_alpha, int32_t n_beta);
 
 /*
  * Upload a Hamiltonian and build the device tables the kernels read
- * (paper section 3.3, the single/double excitation tables; here the
+ * (paper section 4.2, the single/double excitation tables; here the
  * integral slices V_pq[a][b] = (ap|bq) and their antisymmetrised same-spin
  * form).  h1_host, eri_host: host arrays as above.  On success *out owns
  * about 2*n_orb^4*8 bytes of device memory until sci_ham_destroy.  The handle
@@ -92,7 +92,7 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta,
 int32_t sci_ham_destroy(sci_ham_t ham);
 
 /*
- * Coupled-configuration generation (paper section 3.3, Algorithm 1; Eq. 4).
+ * Coupled-configuration generation (paper section 4.2, Algorithm 1; Eq. 4).
  *
  * Flat excitation index f = i*N_c + r for source i in [0, n_dets) and rank
  * r in [0, N_c), N_c = sci_n_coupled(...).  Ranks follow a fixed order per
@@ -131,7 +131,7 @@ int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
 size_t sci_dedup_workspace_bytes(int32_t n_words, int64_t n_cand);
 
 /*
- * Global de-duplication and merge into a running set (paper section 3.2:
+ * Global de-duplication and merge into a running set (paper section 4.1:
  * sort, regular-sampling partition, local unique, merge).
  *
  * cand        device [n_cand][W], any order, duplicates allowed.

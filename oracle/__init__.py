@@ -11,7 +11,7 @@ The arithmetic lives in ``sci_oracle.c`` (plain C, OpenMP over sources):
   paper Eqs. 1-4).
 * ``gen_coupled``   — the coupled set C_i of Eq. 4 (spin-conserving singles and
   doubles) with Slater–Condon elements, operators still applied explicitly.
-* ``dedup_merge``   — sorted set union / difference (section 3.2).
+* ``dedup_merge``   — sorted set union / difference (section 4.1).
 * ``energy``        — Rayleigh quotient of Eq. 1 over the selected space and its
   gradient 2(H psi - E psi)/(psi.psi); ``hpsi_rows`` for sampled rows.
 

@@ -5,7 +5,7 @@
  * library; the only common ground is the determinant encoding below and the
  * seeded input files.
  *
- * What it computes (paper section 2, Eqs. 1-5, and section 3.4):
+ * What it computes (paper section 2.1, Eqs. 1-5, and sections 4.1-4.2):
  *   - the Hamiltonian  H = sum_PQ h_PQ a+_P a_Q
  *                        + 1/2 sum_PQRS <PQ|RS> a+_P a+_Q a_S a_R
  *     over spin orbitals, with h_PQ = h_pq d(sP,sQ) and
@@ -14,7 +14,7 @@
  *     second-quantised form of the Hermitian H of Eq. 1.
  *   - the coupled set C_i of Eq. 4: determinants reached from D_i by moving
  *     one or two occupied positions (spin conserving), with H_ji.
- *   - global de-duplication: the sorted set union of section 3.2.
+ *   - global de-duplication: the sorted set union of section 4.1.
  *   - the Rayleigh quotient of Eq. 1 restricted to the selected space, and its
  *     exact gradient 2(H psi - E psi)/(psi.psi).
  *

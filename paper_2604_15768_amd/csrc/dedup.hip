@@ -1,4 +1,4 @@
-// Global de-duplication on one GPU (paper section 3.2), merged into a running
+// Global de-duplication on one GPU (paper section 4.1), merged into a running
 // set.
 //
 // The paper's three steps map onto one device as follows:
@@ -18,7 +18,7 @@
 // keeping one copy of keys present in both and optionally emitting the keys
 // that were not in the set ("novel").
 //
-// Sort vs. hash (paper section 3.2.2): no hash table and no global atomics on
+// Sort vs. hash (paper section 4.1.2): no hash table and no global atomics on
 // keys; the only atomics are LDS counters.  A bucket larger than the LDS
 // capacity (skewed or heavily repeated keys) is sorted by its workgroup with
 // the same radix ranking over global memory, so every size is handled.

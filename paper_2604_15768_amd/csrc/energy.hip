@@ -6,7 +6,7 @@
 //
 // Membership of j in C_i is decided by pair screening: H_ij can be non-zero
 // only when D_i XOR D_j has two or four set bits (at most two electrons moved,
-// paper section 2).  A workgroup owns 256 rows (one per lane) and streams every
+// paper section 2.1).  A workgroup owns 256 rows (one per lane) and streams every
 // determinant of S through LDS in tiles; all lanes read the same LDS entry at
 // a time (broadcast), so the screening is one XOR + popcount per pair.  For a
 // connected pair the lane rebuilds the excitation from the XOR bits and reads

@@ -1,4 +1,4 @@
-// Coupled-configuration generation (paper section 3.3, Algorithm 1; Eq. 4).
+// Coupled-configuration generation (paper section 4.2, Algorithm 1; Eq. 4).
 //
 // One workgroup takes one (source, rank chunk) tile.  The source determinant
 // is decoded once into LDS: occupied / empty orbital lists per spin, the count

@@ -1,5 +1,5 @@
 // Hamiltonian handle: upload of h1 and (pq|rs), and the device tables the
-// generation and energy kernels read (paper section 3.3: integrals are
+// generation and energy kernels read (paper section 4.2: integrals are
 // pre-arranged per source/target orbitals so a kernel reads one entry per
 // excitation).  Also the ABI's error plumbing and size helpers.
 #include <algorithm>

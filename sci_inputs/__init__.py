@@ -12,8 +12,8 @@ W = ceil(2*n_orb/64) uint64 words; keys compare as unsigned W*64-bit integers
 with word W-1 most significant.  The reference determinant occupies alpha
 orbitals 0..n_alpha-1 and beta orbitals 0..n_beta-1.
 
-Recipe (paper section 2: configurations are bitstrings of length m with n ones;
-section 3.4: source configurations are selected from those coupled to the
+Recipe (paper section 2.1: configurations are bitstrings of length m with n ones;
+section 2.2: selected configurations are drawn from those coupled to the
 reference):
 
 * h: A ~ N(0,1)/n elementwise, h = (A + A^T)/2, then h_pp += -2 + 2p/(n-1).

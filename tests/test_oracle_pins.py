@@ -29,7 +29,7 @@ def _ints(keys):
 
 
 # ---------------------------------------------------------------------------
-# excitation counts and structure (Eq. 4, section 2: at most two moved ones)
+# excitation counts and structure (Eq. 4, section 2.1: at most two moved ones)
 # ---------------------------------------------------------------------------
 
 def _closed_form_count(n, na, nb):
@@ -243,7 +243,7 @@ def test_screening_keeps_strictly_greater():
 
 
 # ---------------------------------------------------------------------------
-# de-duplication set algebra (section 3.2)
+# de-duplication set algebra (section 4.1)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("W", [1, 2])
