@@ -156,7 +156,8 @@ def main():
     # algorithmic bytes per launch of each kernel family (what the work must move at least)
     algo = {
         "gen_kernel": ("hbm", gen_bytes),
-        "bucket_sort_unique_kernel": ("hbm", (n_cand + n_unique) * 8 * W),
+        "bucket_kernel": ("hbm", (n_cand + n_unique) * 8 * W),
+        "emit_kernel": ("hbm", 2 * n_unique * 8 * W),
         "scatter_kernel": ("hbm", 2 * n_cand * 8 * W),
         "hist_kernel": ("hbm", n_cand * 8 * W),
         "merge_kernel": ("hbm", (n_unique + n_sel + n_unique) * 8 * W),

@@ -36,7 +36,7 @@ struct DCfg {
     static constexpr int CAP = (W == 1) ? 4096 : 2048;     // LDS sort capacity (keys)
     static constexpr int K = CAP / kDThreads;              // keys per thread
     static constexpr int CH = CAP / kDWaves;               // keys per wave
-    static constexpr int TARGET = CAP / 2;                 // mean final bucket size
+    static constexpr int TARGET = CAP * 3 / 8;             // mean final bucket size (tail past CAP is rare)
     static constexpr int F1 = 4096;                        // level-1 fan-out bound
     static constexpr int F2 = (W == 1) ? 512 : 256;        // level-2 fan-out bound
     static constexpr int OVS2 = CAP / F2;                  // level-2 oversampling (8)
@@ -318,7 +318,7 @@ __device__ __forceinline__ int64_t seg_size(const int64_t *seg, int s) { return 
 
 // One workgroup per input segment: choose the fan-out, draw regular-stride
 // samples, sort them, pick splitters at equal sample ranks.
-template <int W>
+template <int W, bool GLOBAL_SAMPLES>
 __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     using C = DCfg<W>;
     __shared__ Key<W> s_buf[C::CAP];
@@ -333,7 +333,8 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     if (f == 1) return;
     const int64_t M = std::min<int64_t>(size, std::min<int64_t>((int64_t)a.ovs * f, a.max_samples));
     uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
-    if (M <= C::CAP) {
+    if (!GLOBAL_SAMPLES) {
+        if (M > C::CAP) return;  // cannot happen: the host picks the global variant
         for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
             const int64_t pos = start + (k * size + size / 2) / M;  // regular stride
             s_buf[k] = load_key<W>(a.in, pos);
@@ -435,10 +436,41 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
     for (int j = threadIdx.x; j < f - 1; j += kDThreads) s_spl[j] = load_key<W>(sp, j);
     for (int j = threadIdx.x; j < f; j += kDThreads) s_cnt[j] = 0;
     __syncthreads();
-    for (int64_t i = start + threadIdx.x; i < end; i += kDThreads) {
-        const int b = (f > 1) ? bucket_of<W>(load_key<W>(a.in, i), s_spl, f - 1) : 0;
-        a.ids[i] = (uint16_t)b;
-        atomicAdd(&s_cnt[b], 1u);
+    // four keys per thread in flight: independent fixed-trip searches hide LDS latency
+    const int nspl = f - 1;
+    int top = 1;
+    while (top * 2 <= nspl) top *= 2;
+    for (int64_t i0 = start; i0 < end; i0 += 4 * kDThreads) {
+        Key<W> k[4];
+        int pos[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            ok[u] = i < end;
+            if (ok[u]) k[u] = load_key<W>(a.in, i);
+            else {
+#pragma unroll
+                for (int j = 0; j < W; ++j) k[u].w[j] = 0;
+            }
+            pos[u] = 0;
+        }
+        if (nspl > 0) {
+            for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int nxt = pos[u] + step;
+                    if (nxt <= nspl && key_less<W>(s_spl[nxt - 1], k[u])) pos[u] = nxt;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!ok[u]) continue;
+            const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            a.ids[i] = (uint16_t)pos[u];
+            atomicAdd(&s_cnt[pos[u]], 1u);
+        }
     }
     __syncthreads();
     int64_t *cp = a.counts + a.cbase[s];
@@ -548,112 +580,341 @@ __global__ __launch_bounds__(kDThreads) void scan_apply_kernel(int64_t *x, const
 }
 
 // ---------------------------------------------------------------------------
-// final buckets: LDS radix sort + run-length unique
+// final buckets: LDS radix sort + run-length unique, and the union counts
+// against the running set's keys that fall in each bucket's key range
 // ---------------------------------------------------------------------------
+
+struct BucketArgs {
+    const uint64_t *src;      // partitioned candidates (writable workspace unless single bucket)
+    uint64_t *dst;            // sorted unique run of each bucket, at the bucket's offset
+    const int64_t *seg;       // [n_slots + 1] final bucket offsets
+    int64_t n_slots;
+    int two_level;            // 0: one bucket covering every key
+    const int32_t *fan1;      // [1] level-1 fan-out
+    const uint64_t *spl1;     // [F1-1][W]
+    const int32_t *fan2;      // [F1] level-2 fan-out per level-1 bucket
+    const uint64_t *spl2;     // [F1][F2-1][W]
+    int F2;
+    const uint64_t *B;        // running set (nullable)
+    const int64_t *nB;        // nullable
+    int64_t *nuniq;           // [n_slots] unique candidates per bucket
+    int64_t *bstart;          // [n_slots] first set element in the bucket's key range
+    int64_t *bcount;          // [n_slots] set elements in the range
+    int64_t *ucount;          // [n_slots + 1] union size per bucket (scanned later)
+    int64_t *ncount;          // [n_slots + 1] novel size per bucket (scanned later)
+    int64_t *n_big;           // device count of oversized buckets
+    int64_t *big;             // [n_slots] their slot indices
+};
+
+// number of set elements <= k (upper bound) in B[0..n)
 template <int W>
-__global__ __launch_bounds__(kDThreads) void bucket_sort_unique_kernel(const uint64_t *src, uint64_t *dst,
-                                                                       uint64_t *scratch, const int64_t *seg,
-                                                                       int64_t *ucount) {
+__device__ int64_t upper_bound_set(const uint64_t *B, int64_t n, const Key<W> &k) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key_less<W>(k, load_key<W>(B, mid))) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int W>
+__device__ bool contains_set(const uint64_t *B, int64_t lo, int64_t hi, const Key<W> &k) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const Key<W> m = load_key<W>(B, mid);
+        if (key_less<W>(m, k)) lo = mid + 1;
+        else if (key_less<W>(k, m)) hi = mid;
+        else return true;
+    }
+    return false;
+}
+
+// Key range (lo, hi] of final slot s; returns false for slots that are not buckets.
+template <int W>
+__device__ bool slot_range(const BucketArgs &a, int64_t s, Key<W> &lo, bool &has_lo, Key<W> &hi, bool &has_hi) {
+    has_lo = has_hi = false;
+    if (!a.two_level) return s == 0;
+    const int b1 = (int)(s / a.F2), b2 = (int)(s % a.F2);
+    const int f1 = a.fan1[0];
+    if (b1 >= f1) return false;
+    const int f2 = a.fan2[b1];
+    if (b2 >= f2) return false;
+    const uint64_t *s2 = a.spl2 + (int64_t)b1 * (a.F2 - 1) * W;
+    if (b2 > 0) {
+        lo = load_key<W>(s2, b2 - 1);
+        has_lo = true;
+    } else if (b1 > 0) {
+        lo = load_key<W>(a.spl1, b1 - 1);
+        has_lo = true;
+    }
+    if (b2 < f2 - 1) {
+        hi = load_key<W>(s2, b2);
+        has_hi = true;
+    } else if (b1 < f1 - 1) {
+        hi = load_key<W>(a.spl1, b1);
+        has_hi = true;
+    }
+    return true;
+}
+
+// one thread per final slot: the set elements whose keys fall in the slot's range
+template <int W>
+__global__ void set_range_kernel(BucketArgs a) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const int64_t nB = (a.B && a.nB) ? *a.nB : 0;
+    Key<W> lo, hi;
+    bool hl, hh;
+    int64_t bl = 0, bh = 0;
+    if (nB > 0 && slot_range<W>(a, s, lo, hl, hi, hh)) {
+        bl = hl ? upper_bound_set<W>(a.B, nB, lo) : 0;
+        bh = hh ? upper_bound_set<W>(a.B, nB, hi) : nB;
+        if (bh < bl) bh = bl;
+    }
+    a.bstart[s] = bl;
+    a.bcount[s] = bh - bl;
+}
+
+struct BucketLds {
+    RadixLds R;
+    int64_t brange[2];
+    uint32_t gbase[256], dtot[256];
+    int64_t red[kDWaves];
+};
+
+// 64-bit finaliser mix (multiply / xor-shift) of a key, for the LDS hash table
+template <int W>
+__device__ __forceinline__ uint32_t key_hash(const Key<W> &k) {
+    uint64_t x = k.w[0];
+#pragma unroll
+    for (int j = 1; j < W; ++j) x ^= (k.w[j] << 29) | (k.w[j] >> 35);
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+
+// Rank one digit per lane within the wave (as wave_match_rank), skipping digit
+// bits on which every active lane agrees (uniform ballots need no vector work).
+__device__ __forceinline__ int wave_match_rank_skip(uint32_t d, bool valid, int *rank) {
+    const uint64_t act = __ballot(valid);
+    uint64_t same = act;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+        if (bal != 0ull && bal != act) same &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    *rank = __popcll(same & lanemask_lt());
+    return __popcll(same);
+}
+
+template <int W>
+__global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
-    __shared__ Key<W> s_buf[C::CAP];
-    __shared__ Key<W> s_tmp[C::CAP];
-    __shared__ RadixLds R;
-    __shared__ uint32_t gbase[256], dtot[256];
+    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then the unique keys
+    __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
+    __shared__ uint16_t s_rank[C::CAP];      // per-key rank within its wave and digit
+    __shared__ BucketLds L;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t s = blockIdx.x;
-    const int64_t start = seg[s], size = seg[s + 1] - seg[s];
-    if (size <= 0) {
-        if (threadIdx.x == 0) ucount[s] = 0;
+    const int64_t start = a.seg[s], size = a.seg[s + 1] - a.seg[s];
+    const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
+
+    int64_t nu = 0, matches = 0;
+    if (size > C::CAP) {
+        // sorted by bucket_big_kernel
+        if (threadIdx.x == 0) {
+            const unsigned long long slot = atomicAdd((unsigned long long *)a.n_big, 1ull);
+            a.big[slot] = s;
+        }
         return;
     }
-    int64_t nu_total = 0;
-    if (size <= C::CAP) {
+    if (size > 0) {
         const int m = (int)size;
-        for (int i = threadIdx.x; i < m; i += kDThreads) s_buf[i] = load_key<W>(src, start + i);
+        for (int i = threadIdx.x; i < m; i += kDThreads) s_k0[i] = load_key<W>(a.src, start + i);
+        // hash table of 16-bit key indices (0xffff = empty), two slots per 32-bit word
+        int T = 16;
+        while (T < 2 * m) T <<= 1;
+        uint32_t *tab = reinterpret_cast<uint32_t *>(s_k1);
+        for (int i = threadIdx.x; i < T / 2; i += kDThreads) tab[i] = 0xffffffffu;
         __syncthreads();
-        const Key<W> ref = s_buf[0];
-        const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, R);
-        const Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, m, nbits, R);
-        // run-length unique, in order: K consecutive keys per thread
-        int64_t run = 0;
-        for (int i0 = 0; i0 < m; i0 += kDThreads) {
-            const int i = i0 + threadIdx.x;
-            const bool keep = i < m && (i == 0 || !key_eq<W>(res[i], res[i - 1]));
-            int64_t tot;
-            const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, R.wsum);
-            if (keep) store_key<W>(dst, start + run + ex, res[i]);
-            run += tot;
-            __syncthreads();
+        // one round = 256 consecutive keys; bit r of `fresh` marks a first occurrence in round r
+        uint32_t fresh = 0;
+        const int rounds = (m + kDThreads - 1) / kDThreads;
+        for (int r = 0; r < rounds; ++r) {
+            const int i = r * kDThreads + threadIdx.x;
+            if (i >= m) continue;
+            const Key<W> key = s_k0[i];
+            uint32_t h = key_hash<W>(key) & (uint32_t)(T - 1);
+            while (true) {
+                const uint32_t cur = tab[h >> 1];
+                const uint32_t v = (h & 1u) ? (cur >> 16) : (cur & 0xffffu);
+                if (v == 0xffffu) {
+                    const uint32_t want = (h & 1u) ? ((cur & 0xffffu) | ((uint32_t)i << 16))
+                                                   : ((cur & 0xffff0000u) | (uint32_t)i);
+                    if (atomicCAS(&tab[h >> 1], cur, want) == cur) {
+                        fresh |= 1u << r;
+                        break;
+                    }
+                    continue;  // the word changed: look at this slot again
+                }
+                if (key_eq<W>(s_k0[v], key)) break;  // seen before
+                h = (h + 1u) & (uint32_t)(T - 1);
+            }
         }
-        nu_total = run;
-    } else {
-        // oversized bucket: radix sort over global memory (src range -> dst/src ping-pong)
-        uint64_t *X = const_cast<uint64_t *>(src) + start * W;  // src is level output: writable
-        uint64_t *Y = dst + start * W;
-        const int where = global_radix_sort<W>(X, X, Y, size, R, gbase, dtot);
-        const uint64_t *res = where ? Y : X;
-        // unique into dst range (in place when res == Y: reads stay ahead of writes per tile)
-        int64_t run = 0;
-        for (int64_t i0 = 0; i0 < size; i0 += kDThreads) {
-            const int64_t i = i0 + threadIdx.x;
-            Key<W> cur, prev;
-            bool keep = false;
-            if (i < size) {
-                cur = load_key<W>(res, i);
-                keep = (i == 0);
-                if (i > 0) {
-                    prev = load_key<W>(res, i - 1);
-                    keep = !key_eq<W>(cur, prev);
+        __syncthreads();
+        // compact the first occurrences to the front of s_k0 (in place, round by round)
+        const Key<W> ref = s_k0[0];
+        uint64_t acc[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[j] = 0;
+        int u = 0;
+        for (int r = 0; r < rounds; ++r) {
+            const int i = r * kDThreads + threadIdx.x;
+            const bool keep = (i < m) && ((fresh >> r) & 1u);
+            Key<W> key;
+            if (keep) {
+                key = s_k0[i];
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[j] |= key.w[j] ^ ref.w[j];
+            }
+            int64_t tot;
+            const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, L.R.wsum);  // reads of the round end here
+            if (keep) s_k0[u + ex] = key;
+            u += (int)tot;
+        }
+        if (threadIdx.x == 0) L.R.orx[0] = L.R.orx[1] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (acc[j]) atomicOr((unsigned long long *)&L.R.orx[j], (unsigned long long)acc[j]);
+        __syncthreads();
+        uint64_t o[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) o[j] = L.R.orx[j];
+        const int nbits = varying_bits<W>(o);
+
+        // stable LSD radix sort of the u unique keys, LDS resident
+        Key<W> *cur = s_k0, *nxt = s_k1;
+        const int Kd = (u + kDThreads - 1) / kDThreads;
+        const int CHd = Kd * kWave;
+        for (int shift = 0; shift < nbits; shift += 8) {
+            for (int d = lane; d < 256; d += kWave) L.R.cnt[w][d] = 0;
+            for (int k = 0; k < Kd; ++k) {
+                const int pos = w * CHd + k * kWave + lane;
+                const bool valid = pos < u;
+                const uint32_t d = valid ? digit_of<W>(cur[pos], shift) : 0u;
+                int rk;
+                const int tot = wave_match_rank_skip(d, valid, &rk);
+                uint32_t base = 0;
+                if (valid) base = L.R.cnt[w][d];
+                if (valid && rk == 0) L.R.cnt[w][d] = base + (uint32_t)tot;
+                if (valid) s_rank[pos] = (uint16_t)(base + (uint32_t)rk);
+            }
+            __syncthreads();
+            radix_offsets(L.R, nullptr);
+            __syncthreads();
+            for (int k = 0; k < Kd; ++k) {
+                const int pos = w * CHd + k * kWave + lane;
+                if (pos < u) {
+                    const Key<W> key = cur[pos];
+                    nxt[L.R.cnt[w][digit_of<W>(key, shift)] + s_rank[pos]] = key;
                 }
             }
             __syncthreads();
+            Key<W> *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        // the sorted unique run to the bucket's offset; set hits for the union count
+        int64_t hit = 0;
+        for (int i = threadIdx.x; i < u; i += kDThreads) {
+            const Key<W> key = cur[i];
+            store_key<W>(a.dst, start + i, key);
+            if (bh > bl && contains_set<W>(a.B, bl, bh, key)) ++hit;
+        }
+        nu = u;
+        int64_t ht;
+        block_excl_scan_i64(hit, &ht, L.R.wsum);
+        matches = ht;
+    }
+    if (threadIdx.x == 0) {
+        a.nuniq[s] = nu;
+        a.ucount[s] = nu + (bh - bl) - matches;
+        a.ncount[s] = nu - matches;
+    }
+}
+
+// Oversized buckets (skewed or heavily repeated keys): one workgroup per listed
+// slot sorts over global memory with the same radix ranking, then run-length
+// unique; fixed grid, slots taken in grid-stride order from the device list.
+template <int W>
+__global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
+    __shared__ BucketLds L;
+    const int64_t n_big = *a.n_big;
+    for (int64_t t = blockIdx.x; t < n_big; t += gridDim.x) {
+        const int64_t s = a.big[t];
+        const int64_t start = a.seg[s], size = a.seg[s + 1] - a.seg[s];
+        const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
+        uint64_t *X = const_cast<uint64_t *>(a.src) + start * W;
+        uint64_t *Y = a.dst + start * W;
+        const int where = global_radix_sort<W>(X, X, Y, size, L.R, L.gbase, L.dtot);
+        const uint64_t *res = where ? Y : X;
+        int64_t run = 0, hit = 0;
+        for (int64_t i0 = 0; i0 < size; i0 += kDThreads) {
+            const int64_t i = i0 + threadIdx.x;
+            Key<W> cur;
+            bool keep = false;
+            if (i < size) {
+                cur = load_key<W>(res, i);
+                keep = (i == 0) || !key_eq<W>(cur, load_key<W>(res, i - 1));
+            }
+            __syncthreads();  // every read of this round precedes the writes (in place when res == dst)
+            if (keep && bh > bl && contains_set<W>(a.B, bl, bh, cur)) ++hit;
             int64_t tot;
-            const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, R.wsum);
-            if (keep) store_key<W>(dst, start + run + ex, cur);
+            const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, L.R.wsum);
+            if (keep) store_key<W>(a.dst, start + run + ex, cur);
             run += tot;
             __threadfence();
             __syncthreads();
         }
-        nu_total = run;
-        (void)scratch;
+        int64_t ht;
+        block_excl_scan_i64(hit, &ht, L.R.wsum);
+        if (threadIdx.x == 0) {
+            a.nuniq[s] = run;
+            a.ucount[s] = run + (bh - bl) - ht;
+            a.ncount[s] = run - ht;
+        }
+        __threadfence();
+        __syncthreads();
     }
-    if (threadIdx.x == 0) ucount[s] = nu_total;
-}
-
-// copy each bucket's unique run to its place in the contiguous sorted run
-template <int W>
-__global__ __launch_bounds__(kDThreads) void compact_runs_kernel(const uint64_t *runs, const int64_t *seg,
-                                                                 const int64_t *uoff, uint64_t *out) {
-    const int64_t s = blockIdx.x;
-    const int64_t start = seg[s];
-    const int64_t n = uoff[s + 1] - uoff[s];
-    const int64_t o = uoff[s];
-    for (int64_t i = threadIdx.x; i < n; i += kDThreads) store_key<W>(out, o + i, load_key<W>(runs, start + i));
 }
 
 // ---------------------------------------------------------------------------
-// merge path: run R (sorted unique) with set S (sorted unique)
+// emit: per bucket, merge its unique run with the set elements of its range
+// into set_out at the scanned union offset; novel keys at the novel offset
 // ---------------------------------------------------------------------------
-constexpr int kMergeBlocks = 2048;
-constexpr int kMergePer = 8;  // outputs per thread per round
+constexpr int kMergePer = 8;  // merged positions per thread per round
 
-struct MergeArgs {
-    const uint64_t *A;      // run
-    const int64_t *nA;
-    const uint64_t *B;      // set_in (nullable when empty)
-    const int64_t *nB;      // nullable: 0
+struct EmitArgs {
+    const uint64_t *runs;     // bucket unique runs (at seg offsets)
+    const int64_t *seg;
+    const int64_t *nuniq, *bstart, *bcount;
+    const int64_t *uoff, *noff;  // scanned ucount / ncount
+    const uint64_t *B;
     uint64_t *out;
-    int64_t *n_out;
     int64_t out_cap;
-    uint64_t *novel;        // nullable
-    int64_t *n_novel;
+    uint64_t *novel;          // nullable
     int64_t novel_cap;
-    int64_t *blk;           // [2][kMergeBlocks] unique / novel counts, scanned in place
-    uint32_t *flags;
 };
 
 template <int W>
 __device__ __forceinline__ int64_t merge_path(const uint64_t *A, int64_t nA, const uint64_t *B, int64_t nB,
                                               int64_t k) {
+    // elements of A among the first k of the merge (ties: B first)
     int64_t lo = k > nB ? k - nB : 0, hi = k < nA ? k : nA;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -663,107 +924,102 @@ __device__ __forceinline__ int64_t merge_path(const uint64_t *A, int64_t nA, con
     return lo;
 }
 
-// PASS 0: count unique / novel per block; PASS 1: write.
-template <int W, int PASS>
-__global__ __launch_bounds__(kDThreads) void merge_kernel(MergeArgs a) {
+template <int W>
+__global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
-    const int64_t nA = *a.nA, nB = a.nB ? *a.nB : 0;
-    const int64_t total = nA + nB;
-    const int64_t per = ceil_div_dev(total, (int64_t)kMergeBlocks);
-    const int64_t b0 = (int64_t)blockIdx.x * per;
-    const int64_t b1 = std::min<int64_t>(b0 + per, total);
-    int64_t cu = 0, cn = 0;
-    int64_t base_u = 0, base_n = 0;
-    if (PASS == 1) {
-        base_u = a.blk[blockIdx.x];
-        base_n = a.blk[kMergeBlocks + blockIdx.x];
+    const int64_t s = blockIdx.x;
+    const uint64_t *A = a.runs + a.seg[s] * W;
+    const int64_t nA = a.nuniq[s];
+    const uint64_t *Bs = a.B ? a.B + a.bstart[s] * W : nullptr;
+    const int64_t nBs = a.bcount[s];
+    const int64_t total = nA + nBs;
+    if (total == 0) return;
+    int64_t ou = a.uoff[s], on = a.noff[s];
+    if (nBs == 0) {
+        // common case: the run is the union and all of it is novel
+        for (int64_t i = threadIdx.x; i < nA; i += kDThreads) {
+            const Key<W> k = load_key<W>(A, i);
+            if (ou + i < a.out_cap) store_key<W>(a.out, ou + i, k);
+            if (a.novel && on + i < a.novel_cap) store_key<W>(a.novel, on + i, k);
+        }
+        return;
     }
     const int64_t step = (int64_t)kDThreads * kMergePer;
-    for (int64_t c0 = b0; c0 < b1; c0 += step) {
+    for (int64_t c0 = 0; c0 < total; c0 += step) {
         const int64_t p0 = c0 + (int64_t)threadIdx.x * kMergePer;
-        const int64_t p1 = std::min<int64_t>(p0 + kMergePer, b1);
-        int64_t i = 0, j = 0;
-        uint32_t fa = 0, fd = 0;  // per output: from A, duplicate
+        const int64_t p1 = p0 + kMergePer < total ? p0 + kMergePer : total;
         Key<W> vals[kMergePer];
+        uint32_t fa = 0, fd = 0;
         int cnt = 0;
         if (p0 < p1) {
-            i = merge_path<W>(a.A, nA, a.B, nB, p0);
-            j = p0 - i;
-            for (int64_t p = p0; p < p1; ++p, ++cnt) {
-                bool takeA;
-                if (i >= nA) takeA = false;
-                else if (j >= nB) takeA = true;
-                else takeA = key_less<W>(load_key<W>(a.A, i), load_key<W>(a.B, j));
-                if (takeA) {
-                    const Key<W> x = load_key<W>(a.A, i);
-                    const bool dup = (j > 0) && key_eq<W>(load_key<W>(a.B, j - 1), x);
-                    vals[cnt] = x;
-                    fa |= 1u << cnt;
-                    if (dup) fd |= 1u << cnt;
-                    ++i;
-                } else {
-                    vals[cnt] = load_key<W>(a.B, j);
-                    ++j;
+            int64_t i = merge_path<W>(A, nA, Bs, nBs, p0);
+            int64_t j = p0 - i;
+            cnt = (int)(p1 - p0);
+#pragma unroll
+            for (int q = 0; q < kMergePer; ++q) {
+                if (q < cnt) {
+                    bool takeA;
+                    if (i >= nA) takeA = false;
+                    else if (j >= nBs) takeA = true;
+                    else takeA = key_less<W>(load_key<W>(A, i), load_key<W>(Bs, j));
+                    if (takeA) {
+                        const Key<W> x = load_key<W>(A, i);
+                        vals[q] = x;
+                        fa |= 1u << q;
+                        if (j > 0 && key_eq<W>(load_key<W>(Bs, j - 1), x)) fd |= 1u << q;
+                        ++i;
+                    } else {
+                        vals[q] = load_key<W>(Bs, j);
+                        ++j;
+                    }
                 }
             }
         }
         int lu = 0, ln = 0;
-        for (int q = 0; q < cnt; ++q) {
+#pragma unroll
+        for (int q = 0; q < kMergePer; ++q) {
             const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
-            lu += !dup;
-            ln += fromA && !dup;
+            lu += (q < cnt) && !dup;
+            ln += (q < cnt) && fromA && !dup;
         }
         int64_t tu, tn;
         const int64_t eu = block_excl_scan_i64(lu, &tu, wsum);
-        __syncthreads();
         const int64_t en = block_excl_scan_i64(ln, &tn, wsum);
-        __syncthreads();
-        if (PASS == 1) {
-            int64_t ou = base_u + cu + eu, on = base_n + cn + en;
-            for (int q = 0; q < cnt; ++q) {
-                const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
-                if (dup) continue;
-                if (ou < a.out_cap) store_key<W>(a.out, ou, vals[q]);
-                ++ou;
-                if (fromA && a.novel) {
-                    if (on < a.novel_cap) store_key<W>(a.novel, on, vals[q]);
-                    ++on;
-                }
+        int64_t pu = ou + eu, pn = on + en;
+#pragma unroll
+        for (int q = 0; q < kMergePer; ++q) {
+            const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
+            if (q >= cnt || dup) continue;
+            if (pu < a.out_cap) store_key<W>(a.out, pu, vals[q]);
+            ++pu;
+            if (fromA) {
+                if (a.novel && pn < a.novel_cap) store_key<W>(a.novel, pn, vals[q]);
+                ++pn;
             }
         }
-        cu += tu;
-        cn += tn;
-    }
-    if (PASS == 0 && threadIdx.x == 0) {
-        a.blk[blockIdx.x] = cu;
-        a.blk[kMergeBlocks + blockIdx.x] = cn;
+        ou += tu;
+        on += tn;
     }
 }
 
-__global__ __launch_bounds__(kDThreads) void merge_scan_kernel(MergeArgs a) {
-    __shared__ int64_t wsum[kDWaves];
-    for (int part = 0; part < 2; ++part) {
-        int64_t *x = a.blk + part * kMergeBlocks;
-        int64_t run = 0;
-        for (int b0 = 0; b0 < kMergeBlocks; b0 += kDThreads) {
-            const int b = b0 + threadIdx.x;
-            const int64_t v = x[b];
-            int64_t tot;
-            const int64_t ex = block_excl_scan_i64(v, &tot, wsum);
-            x[b] = run + ex;
-            run += tot;
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (part == 0) {
-                *a.n_out = run;
-                if (run > a.out_cap) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
-            } else if (a.n_novel) {
-                *a.n_novel = run;
-                if (a.novel && run > a.novel_cap) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
-            }
-        }
-        __syncthreads();
+// empty candidate list: the union is the set itself
+template <int W>
+__global__ void copy_keys_kernel(const uint64_t *B, const int64_t *nB, uint64_t *out, int64_t cap) {
+    const int64_t n = nB ? *nB : 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n && i < cap;
+         i += (int64_t)gridDim.x * blockDim.x)
+        store_key<W>(out, i, load_key<W>(B, i));
+}
+
+__global__ void finish_counts_kernel(const int64_t *total_u, const int64_t *total_n, int64_t *n_out, int64_t out_cap,
+                                     int64_t *n_novel, int64_t novel_cap, int novel_given, uint32_t *flags) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t u = *total_u;
+    *n_out = u;
+    if (u > out_cap) atomicOr(flags, SCI_FLAG_OVERFLOW);
+    if (n_novel) {
+        *n_novel = *total_n;
+        if (novel_given && *total_n > novel_cap) atomicOr(flags, SCI_FLAG_OVERFLOW);
     }
 }
 
@@ -782,7 +1038,8 @@ __global__ void check_sorted_kernel(const uint64_t *S, const int64_t *nS, uint32
 // host orchestration
 // ---------------------------------------------------------------------------
 struct WsLayout {
-    size_t bufA, bufB, ids, segA, segB, fan, spl, tile_base, cbase, counts, sums, samples, ucount, blk, scal;
+    size_t bufA, bufB, ids, segA, segB, fan1, fan2, spl1, spl2, tile_base, cbase, counts, sums, samples;
+    size_t nuniq, bstart, bcount, ucount, ncount, big, scal;
     size_t total;
     int64_t max_counts, max_sums, n_final_slots;
 };
@@ -811,15 +1068,21 @@ static WsLayout ws_layout(int64_t n) {
     L.ids = take((size_t)nn * 2);
     L.segA = take((size_t)(S2 + 1) * 8);
     L.segB = take((size_t)(S2 + 1) * 8);
-    L.fan = take((size_t)S1 * 4);
-    L.spl = take((size_t)S1 * (C::F2 > C::F1 ? C::F2 : C::F1) * W * 8);
+    L.fan1 = take(64);
+    L.fan2 = take((size_t)S1 * 4);
+    L.spl1 = take((size_t)C::F1 * W * 8);
+    L.spl2 = take((size_t)S1 * C::F2 * W * 8);
     L.tile_base = take((size_t)(S1 + 1) * 8);
     L.cbase = take((size_t)(S1 + 1) * 8);
-    L.counts = take((size_t)std::max<int64_t>(L.max_counts, S2 + 1) * 8);
+    L.counts = take((size_t)L.max_counts * 8);
     L.sums = take((size_t)L.max_sums * 8);
     L.samples = take((size_t)C::M1 * 2 * W * 8);
+    L.nuniq = take((size_t)S2 * 8);
+    L.bstart = take((size_t)S2 * 8);
+    L.bcount = take((size_t)S2 * 8);
     L.ucount = take((size_t)(S2 + 1) * 8);
-    L.blk = take((size_t)2 * kMergeBlocks * 8);
+    L.ncount = take((size_t)(S2 + 1) * 8);
+    L.big = take((size_t)S2 * 8);
     L.scal = take(64);
     L.total = off;
     return L;
@@ -828,11 +1091,9 @@ static WsLayout ws_layout(int64_t n) {
 static hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_t *sums, int64_t *total_out,
                               hipStream_t st) {
     const int64_t nb = std::max<int64_t>(1, ceil_div(n_bound, kScanPer));
-    SCI_LAUNCH(scan_reduce_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, (const int64_t *)x, n_dev,
-                       n_bound, sums);
+    SCI_LAUNCH(scan_reduce_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, (const int64_t *)x, n_dev, n_bound, sums);
     SCI_LAUNCH(scan_sums_kernel, dim3(1), dim3(kDThreads), 0, st, sums, nb, total_out);
-    SCI_LAUNCH(scan_apply_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, x, n_dev, n_bound,
-                       (const int64_t *)sums);
+    SCI_LAUNCH(scan_apply_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, x, n_dev, n_bound, (const int64_t *)sums);
     return hipGetLastError();
 }
 
@@ -851,120 +1112,142 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     const WsLayout L = ws_layout<W>(n);
     uint64_t *bufA = (uint64_t *)(ws + L.bufA);
     uint64_t *bufB = (uint64_t *)(ws + L.bufB);
-    uint16_t *ids = (uint16_t *)(ws + L.ids);
     int64_t *segA = (int64_t *)(ws + L.segA);
     int64_t *segB = (int64_t *)(ws + L.segB);
     int64_t *counts = (int64_t *)(ws + L.counts);
     int64_t *sums = (int64_t *)(ws + L.sums);
-    int64_t *ucount = (int64_t *)(ws + L.ucount);
-    int64_t *scal = (int64_t *)(ws + L.scal);  // [0]: |run|, [1]: counts total
-    int64_t *nrun = scal;
+    int64_t *scal = (int64_t *)(ws + L.scal);  // [0] union total, [1] novel total, [2] level counters
+    const bool have_set = set_in && n_set_in;
 
-    const uint64_t *run = nullptr;  // sorted unique candidates
-    if (n > 0) {
+    if (have_set)
+        SCI_LAUNCH(check_sorted_kernel<W>, dim3(1024), dim3(256), 0, st, set_in, n_set_in, flags);
+    if (n == 0) {
+        SCI_LAUNCH(copy_keys_kernel<W>, dim3(4096), dim3(256), 0, st, set_in, have_set ? n_set_in : nullptr, set_out,
+                   set_cap);
+        if (have_set) {
+            SCI_HIP_TRY(launch_set_i64(scal + 1, 0, st));
+            SCI_LAUNCH(finish_counts_kernel, dim3(1), dim3(64), 0, st, n_set_in, (const int64_t *)(scal + 1),
+                       n_set_out, set_cap, n_novel, novel_cap, novel ? 1 : 0, flags);
+        } else {
+            SCI_HIP_TRY(launch_set_i64(n_set_out, 0, st));
+            if (n_novel) SCI_HIP_TRY(launch_set_i64(n_novel, 0, st));
+        }
+        return SCI_OK;
+    }
+
+    BucketArgs b{};
+    SCI_LAUNCH(init_level0_kernel, dim3(1), dim3(64), 0, st, segA, n);
+    if (n <= C::CAP) {
+        b.src = cand;  // one bucket: read only
+        b.seg = segA;
+        b.n_slots = 1;
+        b.two_level = 0;
+    } else {
         const uint64_t *cur = cand;
         const int64_t *seg_cur = segA;
         int S_cur = 1;
-        SCI_LAUNCH(init_level0_kernel, dim3(1), dim3(64), 0, st, segA, n);
-        uint64_t *sort_src;
-        const int64_t *final_seg;
-        int64_t n_final;
-        if (n <= C::CAP) {
-            sort_src = const_cast<uint64_t *>(cand);  // read only: size <= CAP never writes src
-            final_seg = segA;
-            n_final = 1;
-        } else {
-            // level 1: one segment -> up to F1 buckets; level 2: each -> up to F2 buckets
-            for (int lvl = 0; lvl < 2; ++lvl) {
-                LevelArgs a{};
-                a.in = cur;
-                a.out = (lvl == 0) ? bufA : bufB;
-                a.ids = ids;
-                a.seg_in = seg_cur;
-                a.seg_out = (lvl == 0) ? segB : segA;
-                a.S_in = S_cur;
-                a.F = (lvl == 0) ? C::F1 : C::F2;
-                a.tile = (lvl == 0) ? C::TILE1 : C::TILE2;
-                if (lvl == 0) {
-                    // level-1 buckets sized so level 2 splits each into about F2/2 final buckets
-                    a.target = (int)std::min<int64_t>((int64_t)C::TARGET * (C::F2 / 2), 1ll << 30);
-                    a.ovs = 16;
-                    a.max_samples = C::M1;
-                } else {
-                    a.target = C::TARGET;
-                    a.ovs = C::OVS2;
-                    a.max_samples = C::CAP;
-                }
-                a.fan = (int32_t *)(ws + L.fan);
-                a.spl = (uint64_t *)(ws + L.spl);
-                a.tile_base = (int64_t *)(ws + L.tile_base);
-                a.cbase = (int64_t *)(ws + L.cbase);
-                a.counts = counts;
-                a.sample_buf = (uint64_t *)(ws + L.samples);
-                const int64_t tiles_bound = ceil_div(n, a.tile) + S_cur;
-                a.max_tiles = tiles_bound;
-                SCI_LAUNCH(splitter_kernel<W>, dim3(S_cur), dim3(kDThreads), 0, st, a);
-                SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
-                if (lvl == 0) {
-                    SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
-                } else {
-                    SCI_LAUNCH((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
-                }
-                SCI_HIP_TRY(hipGetLastError());
-                // exclusive scan of all counters -> absolute output offsets
-                const int64_t cbound = tiles_bound * (int64_t)a.F;
-                SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 1, st));
-                if (lvl == 0) {
-                    SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
-                } else {
-                    SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
-                }
-                const int64_t slots = (int64_t)S_cur * a.F;
-                SCI_LAUNCH(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
-                SCI_HIP_TRY(hipGetLastError());
-                cur = a.out;
-                seg_cur = a.seg_out;
-                S_cur = (int)slots;
+        for (int lvl = 0; lvl < 2; ++lvl) {
+            LevelArgs a{};
+            a.in = cur;
+            a.out = (lvl == 0) ? bufA : bufB;
+            a.ids = (uint16_t *)(ws + L.ids);
+            a.seg_in = seg_cur;
+            a.seg_out = (lvl == 0) ? segB : segA;
+            a.S_in = S_cur;
+            a.F = (lvl == 0) ? C::F1 : C::F2;
+            a.tile = (lvl == 0) ? C::TILE1 : C::TILE2;
+            if (lvl == 0) {
+                // level-1 buckets sized so level 2 splits each into about F2/2 final buckets
+                a.target = (int)std::min<int64_t>((int64_t)C::TARGET * (C::F2 / 2), 1ll << 30);
+                a.ovs = 16;
+                a.max_samples = C::M1;
+                a.fan = (int32_t *)(ws + L.fan1);
+                a.spl = (uint64_t *)(ws + L.spl1);
+            } else {
+                a.target = C::TARGET;
+                a.ovs = C::OVS2;
+                a.max_samples = C::CAP;
+                a.fan = (int32_t *)(ws + L.fan2);
+                a.spl = (uint64_t *)(ws + L.spl2);
             }
-            sort_src = bufB;
-            final_seg = segA;  // level-2 output segments
-            n_final = S_cur;
+            a.tile_base = (int64_t *)(ws + L.tile_base);
+            a.cbase = (int64_t *)(ws + L.cbase);
+            a.counts = counts;
+            a.sample_buf = (uint64_t *)(ws + L.samples);
+            const int64_t tiles_bound = ceil_div(n, a.tile) + S_cur;
+            a.max_tiles = tiles_bound;
+            if (a.max_samples > C::CAP) {
+                SCI_LAUNCH((splitter_kernel<W, true>), dim3(S_cur), dim3(kDThreads), 0, st, a);
+            } else {
+                SCI_LAUNCH((splitter_kernel<W, false>), dim3(S_cur), dim3(kDThreads), 0, st, a);
+            }
+            SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
+            if (lvl == 0) {
+                SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+            } else {
+                SCI_LAUNCH((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+            }
+            SCI_HIP_TRY(hipGetLastError());
+            // exclusive scan of all counters -> absolute output offsets
+            const int64_t cbound = tiles_bound * (int64_t)a.F;
+            SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 2, st));
+            if (lvl == 0) {
+                SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+            } else {
+                SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+            }
+            const int64_t slots = (int64_t)S_cur * a.F;
+            SCI_LAUNCH(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
+            SCI_HIP_TRY(hipGetLastError());
+            cur = a.out;
+            seg_cur = a.seg_out;
+            S_cur = (int)slots;
         }
-        // sorted unique runs per final bucket, written into bufA at the bucket offsets
-        SCI_LAUNCH(bucket_sort_unique_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
-                           (const uint64_t *)sort_src, bufA, bufB, final_seg, ucount);
-        SCI_HIP_TRY(hipGetLastError());
-        SCI_HIP_TRY(launch_set_i64(ucount + n_final, 0, st));
-        SCI_HIP_TRY(device_scan(ucount, nullptr, n_final + 1, sums, nrun, st));
-        uint64_t *dest = bufB;  // free once the buckets are sorted
-        SCI_LAUNCH(compact_runs_kernel<W>, dim3((unsigned)n_final), dim3(kDThreads), 0, st,
-                           (const uint64_t *)bufA, final_seg, (const int64_t *)ucount, dest);
-        SCI_HIP_TRY(hipGetLastError());
-        run = dest;
-    } else {
-        SCI_HIP_TRY(launch_set_i64(nrun, 0, st));
-        run = (uint64_t *)(ws + L.bufA);
+        b.src = bufB;
+        b.seg = segA;  // level-2 output segments
+        b.n_slots = S_cur;
+        b.two_level = 1;
     }
-
-    // merge the run into the set
-    if (set_in && n_set_in)
-        SCI_LAUNCH(check_sorted_kernel<W>, dim3(1024), dim3(256), 0, st, set_in, n_set_in, flags);
-    MergeArgs m{};
-    m.A = run;
-    m.nA = nrun;
-    m.B = set_in;
-    m.nB = (set_in && n_set_in) ? n_set_in : nullptr;
-    m.out = set_out;
-    m.n_out = n_set_out;
-    m.out_cap = set_cap;
-    m.novel = novel;
-    m.n_novel = n_novel;
-    m.novel_cap = novel_cap;
-    m.blk = (int64_t *)(ws + L.blk);
-    m.flags = flags;
-    SCI_LAUNCH((merge_kernel<W, 0>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
-    SCI_LAUNCH(merge_scan_kernel, dim3(1), dim3(kDThreads), 0, st, m);
-    SCI_LAUNCH((merge_kernel<W, 1>), dim3(kMergeBlocks), dim3(kDThreads), 0, st, m);
+    b.dst = bufA;
+    b.fan1 = (const int32_t *)(ws + L.fan1);
+    b.spl1 = (const uint64_t *)(ws + L.spl1);
+    b.fan2 = (const int32_t *)(ws + L.fan2);
+    b.spl2 = (const uint64_t *)(ws + L.spl2);
+    b.F2 = C::F2;
+    b.B = have_set ? set_in : nullptr;
+    b.nB = have_set ? n_set_in : nullptr;
+    b.nuniq = (int64_t *)(ws + L.nuniq);
+    b.bstart = (int64_t *)(ws + L.bstart);
+    b.bcount = (int64_t *)(ws + L.bcount);
+    b.ucount = (int64_t *)(ws + L.ucount);
+    b.ncount = (int64_t *)(ws + L.ncount);
+    SCI_LAUNCH(set_range_kernel<W>, dim3((unsigned)ceil_div(b.n_slots, 256)), dim3(256), 0, st, b);
+    b.n_big = scal + 3;
+    b.big = (int64_t *)(ws + L.big);
+    SCI_HIP_TRY(launch_set_i64(b.n_big, 0, st));
+    SCI_LAUNCH(bucket_kernel<W>, dim3((unsigned)b.n_slots), dim3(kDThreads), 0, st, b);
+    SCI_LAUNCH(bucket_big_kernel<W>, dim3(4096), dim3(kDThreads), 0, st, b);
+    SCI_HIP_TRY(hipGetLastError());
+    SCI_HIP_TRY(launch_set_i64(b.ucount + b.n_slots, 0, st));
+    SCI_HIP_TRY(launch_set_i64(b.ncount + b.n_slots, 0, st));
+    SCI_HIP_TRY(device_scan(b.ucount, nullptr, b.n_slots + 1, sums, scal + 0, st));
+    SCI_HIP_TRY(device_scan(b.ncount, nullptr, b.n_slots + 1, sums, scal + 1, st));
+    EmitArgs e{};
+    e.runs = bufA;
+    e.seg = b.seg;
+    e.nuniq = b.nuniq;
+    e.bstart = b.bstart;
+    e.bcount = b.bcount;
+    e.uoff = b.ucount;
+    e.noff = b.ncount;
+    e.B = b.B;
+    e.out = set_out;
+    e.out_cap = set_cap;
+    e.novel = novel;
+    e.novel_cap = novel_cap;
+    SCI_LAUNCH(emit_kernel<W>, dim3((unsigned)b.n_slots), dim3(kDThreads), 0, st, e);
+    SCI_LAUNCH(finish_counts_kernel, dim3(1), dim3(64), 0, st, (const int64_t *)(scal + 0),
+               (const int64_t *)(scal + 1), n_set_out, set_cap, n_novel, novel_cap, novel ? 1 : 0, flags);
     SCI_HIP_TRY(hipGetLastError());
     return SCI_OK;
 }

@@ -308,3 +308,32 @@ def test_energy_flags():
     _, _, _, flags = sci.energy(h, sel, torch.from_numpy(s.psi).cuda())
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "energy", allow=sci.FLAG_UNSORTED) & sci.FLAG_UNSORTED
+
+
+@pytest.mark.parametrize("W", [1, 2])
+@pytest.mark.parametrize("n_cand", [1000, 3000, 300_000])
+def test_dedup_large_set_few_candidates(W, n_cand):
+    """Running set much larger than the candidate batch: many set keys per bucket range,
+    keys below/above every candidate, half of the candidates already in the set."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(900 + W + n_cand))
+    setk = si.sort_keys(np.unique(_random_keys(rng, 200_000, W, pool=400_000), axis=0))
+    fresh = _random_keys(rng, n_cand // 2, W, pool=n_cand)
+    old = setk[rng.integers(0, setk.shape[0], n_cand - n_cand // 2)]
+    cand = np.concatenate([fresh, old])
+    cand = cand[rng.permutation(cand.shape[0])]
+    say(f"dedup large set W={W} n_cand={n_cand} n_set={setk.shape[0]}")
+    _dedup_check(sci, cand, setk, W)
+
+
+@pytest.mark.parametrize("W", [1, 2])
+def test_dedup_streamed_chunks(W):
+    """Two candidate batches merged one after the other equal one merge of both."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(77 + W))
+    c0 = _random_keys(rng, 150_000, W, pool=90_000)
+    c1 = np.concatenate([c0[:40_000], _random_keys(rng, 110_000, W, pool=70_000)])
+    empty = np.zeros((0, W), np.uint64)
+    u0, _ = oracle.dedup_merge(W, c0, empty)
+    _dedup_check(sci, c0, empty, W)
+    _dedup_check(sci, c1, u0, W)
