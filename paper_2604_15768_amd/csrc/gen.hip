@@ -1,25 +1,26 @@
 // Coupled-configuration generation (paper section 4.2, Algorithm 1; Eq. 4).
 //
-// One workgroup takes one (source, rank chunk) tile.  The source determinant
-// is decoded once into LDS: occupied / empty orbital lists per spin, the count
-// of occupied orbitals below every orbital (for fermionic signs), and the
-// lexicographic pair lists used to unrank double excitations.  Every lane
-// then maps its rank to (class, p, q, a, b), flips bits of the source to form
-// the new key, reads one integral-table entry for a double (or sums the
-// occupied-orbital terms for a single), applies the sign and writes key and
-// H_ij with unit-stride stores (one wave writes 64 consecutive entries).
+// One workgroup per source determinant.  The source is decoded once into LDS:
+// occupied / empty orbital lists per spin, the count of occupied orbitals below
+// every orbital (for fermionic signs), and the lexicographic pair lists used to
+// unrank same-spin doubles.  Its excitations are processed in rows that share
+// their holes; each wave takes whole rows, so the row's partial key, integral
+// row and per-particle sign bits are wave-uniform, and lanes step through the
+// particles of the row with unit-stride stores (one wave writes 64 consecutive
+// entries).
 //
 // Unlike the paper's padded virtual-thread space (Eqs. 6-7), ranks cover only
 // valid excitations, so dense mode needs no compaction and its output order is
 // fixed.  Screened mode (eps >= 0) keeps |H| > eps and compacts with a wave
-// ballot and one atomic per workgroup iteration (the paper's block-wide
-// compaction with a single atomicAdd per block).
+// ballot and one atomic per wave iteration (the paper compacts per block with
+// one atomicAdd per block).
 #include "sci_internal.hpp"
 
 namespace sci {
 
 constexpr int kGenThreads = 256;
 constexpr int kMaxPairs = 64 * 63 / 2;
+constexpr int kUnroll = 4;  // row positions per lane per loop trip (loads issued before stores)
 
 struct GenArgs {
     // system
@@ -30,7 +31,7 @@ struct GenArgs {
     // tiles
     const uint64_t *dets;
     int64_t src_first;
-    int chunk, chunks_per_src;
+    int pva, pvb;  // C(v_alpha, 2), C(v_beta, 2)
     int64_t exc_begin, exc_end;
     // outputs
     uint64_t *keys;
@@ -40,19 +41,18 @@ struct GenArgs {
     unsigned long long *n_out;
     uint32_t *flags;
     double eps;
-    // fast division
-    FastDiv d_va, d_vb, d_nb, d_vab, d_pva, d_pvb;
 };
 
+constexpr int kMaxSingles = 512;  // per spin; larger systems compute singles per lane
+
 struct GenLds {
+    double sval[2][kMaxSingles];  // single-excitation elements (unsigned) of the source, [ip * v + ia]
     uint8_t occ[2][64];
     uint8_t vir[2][64];
     uint8_t below[2][64];  // occupied orbitals of the same spin strictly below p
     uint16_t pocc[2][kMaxPairs];
     uint16_t pvir[2][kMaxPairs];
     int bad;
-    int wave_tot[kGenThreads / kWave];
-    unsigned long long slab;
 };
 
 __device__ __forceinline__ void copy_pairs(uint16_t *dst, const uint16_t *src, int m, int tid) {
@@ -60,88 +60,66 @@ __device__ __forceinline__ void copy_pairs(uint16_t *dst, const uint16_t *src, i
     for (int t = tid; t < total; t += kGenThreads) dst[t] = src[t];
 }
 
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | (uint64_t)uni((uint32_t)x);
+}
+
 template <int W>
-__device__ __forceinline__ void gen_one(const GenArgs &a, const GenLds &L, const Key<W> &src, int r,
-                                        Key<W> &key, double &h) {
-    const int n = a.n;
-    key = src;
-    if (r < a.c2) {
-        // single excitation p -> a within one spin
-        const int sg = r < a.c1 ? 0 : 1;
-        const uint32_t x = (uint32_t)(sg ? r - a.c1 : r);
-        uint32_t ia;
-        const uint32_t ip = fdiv(x, sg ? a.d_vb : a.d_va, ia);
-        const int p = L.occ[sg][ip];
-        const int t = L.vir[sg][ia];
-        const int off = sg * n;
-        key_flip<W>(key, p + off);
-        key_flip<W>(key, t + off);
-        const int par = L.below[sg][p] + L.below[sg][t] - (p < t ? 1 : 0);
-        // h_ap + sum over occupied Q != P of [(ap|qq) - delta_spin (aq|qp)], Q ascending
-        double v = a.h1[t * n + p];
-        const int nocc0 = a.na, nocc1 = a.nb;
-        for (int s2 = 0; s2 < 2; ++s2) {
-            const int cnt = s2 ? nocc1 : nocc0;
-            for (int k = 0; k < cnt; ++k) {
-                const int q = L.occ[s2][k];
-                if (s2 == sg && q == p) continue;
-                const double j = a.eri[((int64_t)(t * n + p) * n + q) * n + q];
-                const double kx = (s2 == sg) ? a.eri[((int64_t)(t * n + q) * n + q) * n + p] : 0.0;
-                v += j - kx;
+__device__ __forceinline__ Key<W> uni_key(const Key<W> &k) {
+    Key<W> r;
+#pragma unroll
+    for (int j = 0; j < W; ++j) r.w[j] = uni64(k.w[j]);
+    return r;
+}
+
+// Write one output slot (dense) or compact it through one atomic per wave (screened).
+template <int W, bool DENSE>
+__device__ __forceinline__ void emit(const GenArgs &a, int64_t o_dense, bool valid, const Key<W> &key, double h,
+                                     int64_t src) {
+    if constexpr (DENSE) {
+        if (valid) {
+            store_key<W>(a.keys, o_dense, key);
+            a.hij[o_dense] = h;
+            if (a.src_out) a.src_out[o_dense] = (int32_t)src;
+        }
+    } else {
+        const bool keep = valid && fabs(h) > a.eps;
+        const unsigned long long m = __ballot(keep);
+        if (m == 0ull) return;
+        const int lane = threadIdx.x & (kWave - 1);
+        unsigned long long base = 0;
+        if (lane == 0) {
+            base = atomicAdd(a.n_out, (unsigned long long)__popcll(m));
+            if ((int64_t)(base + __popcll(m)) > a.capacity) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
+        }
+        base = __shfl(base, 0);
+        if (keep) {
+            const int64_t o = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+            if (o < a.capacity) {
+                store_key<W>(a.keys, o, key);
+                a.hij[o] = h;
+                a.src_out[o] = (int32_t)src;
             }
         }
-        h = (par & 1) ? -v : v;
-    } else if (r < a.c4) {
-        // same-spin double p<q -> a<b
-        const int sg = r < a.c3 ? 0 : 1;
-        const uint32_t x = (uint32_t)(r - (sg ? a.c3 : a.c2));
-        uint32_t tv;
-        const uint32_t o = fdiv(x, sg ? a.d_pvb : a.d_pva, tv);
-        const uint16_t po = L.pocc[sg][o];
-        const uint16_t pv = L.pvir[sg][tv];
-        const int p = L.occ[sg][po & 0xff], q = L.occ[sg][po >> 8];
-        const int ta = L.vir[sg][pv & 0xff], tb = L.vir[sg][pv >> 8];
-        const int off = sg * n;
-        key_flip<W>(key, p + off);
-        key_flip<W>(key, q + off);
-        key_flip<W>(key, ta + off);
-        key_flip<W>(key, tb + off);
-        const int par = L.below[sg][p] + L.below[sg][q] - 1 + L.below[sg][tb] - (p < tb) - (q < tb) +
-                        L.below[sg][ta] - (p < ta) - (q < ta);
-        const double v = a.vanti[((int64_t)(p * n + q) * n + ta) * n + tb];
-        h = (par & 1) ? -v : v;
-    } else {
-        // alpha-beta double p(alpha) q(beta) -> a(alpha) b(beta)
-        const uint32_t x = (uint32_t)(r - a.c4);
-        uint32_t t;
-        const uint32_t o = fdiv(x, a.d_vab, t);
-        uint32_t iq, ib;
-        const uint32_t ip = fdiv(o, a.d_nb, iq);
-        const uint32_t ia = fdiv(t, a.d_vb, ib);
-        const int p = L.occ[0][ip], q = L.occ[1][iq];
-        const int ta = L.vir[0][ia], tb = L.vir[1][ib];
-        key_flip<W>(key, p);
-        key_flip<W>(key, ta);
-        key_flip<W>(key, q + n);
-        key_flip<W>(key, tb + n);
-        const int par = L.below[0][p] + L.below[0][ta] - (p < ta) + L.below[1][q] + L.below[1][tb] - (q < tb);
-        const double v = a.vdir[((int64_t)(p * n + q) * n + ta) * n + tb];
-        h = (par & 1) ? -v : v;
     }
 }
 
+// One workgroup per source.  The source's excitations are organised in rows
+// that share their holes: a single row per occupied orbital p (singles), per
+// occupied pair p<q (same-spin doubles) and per (p alpha, q beta) (mixed
+// doubles).  Waves take rows round-robin; inside a row every hole-dependent
+// quantity (row key, integral row base, per-particle sign bits gathered with a
+// ballot) is wave-uniform and lanes walk the particle index without division.
 template <int W, bool DENSE>
 __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
     __shared__ GenLds L;
     const int tid = threadIdx.x;
-    const int64_t src = a.src_first + blockIdx.x / a.chunks_per_src;
-    const int chunk_id = blockIdx.x % a.chunks_per_src;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t src = a.src_first + blockIdx.x;
     const int64_t flat0 = src * a.nc;
-    int64_t lo = flat0 + (int64_t)chunk_id * a.chunk;
-    int64_t hi = lo + a.chunk;
-    if (hi > flat0 + a.nc) hi = flat0 + a.nc;
-    if (lo < a.exc_begin) lo = a.exc_begin;
-    if (hi > a.exc_end) hi = a.exc_end;
+    const int64_t lo = (a.exc_begin > flat0 ? a.exc_begin : flat0) - flat0;
+    const int64_t hi = (a.exc_end < flat0 + a.nc ? a.exc_end : flat0 + a.nc) - flat0;
     if (lo >= hi) return;  // uniform per workgroup
 
     const Key<W> s = load_key<W>(a.dets, src);
@@ -158,7 +136,10 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
         const int k = tid;
         const int below_all = key_popc_below<W>(s, k);
         const int below_same = sg ? below_all - key_popc_below<W>(s, n) : below_all;
-        const bool occ = (s.w[k >> 6] >> (k & 63)) & 1ull;
+        uint64_t word = s.w[0];
+#pragma unroll
+        for (int j = 1; j < W; ++j) word = ((k >> 6) == j) ? s.w[j] : word;
+        const bool occ = (word >> (k & 63)) & 1ull;
         L.below[sg][p] = (uint8_t)below_same;
         if (occ) {
             if (below_same < 64) L.occ[sg][below_same] = (uint8_t)p;
@@ -172,64 +153,212 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
     copy_pairs(L.pvir[0], a.pairs[2], a.va, tid);
     copy_pairs(L.pvir[1], a.pairs[3], a.vb, tid);
     __syncthreads();
-
-    const bool bad = L.bad != 0;
-    if (bad && tid == 0) atomicOr(a.flags, SCI_FLAG_BAD_DET);
-    const int r_lo = (int)(lo - flat0), r_hi = (int)(hi - flat0);
-
-    if constexpr (DENSE) {
-        for (int r = r_lo + tid; r < r_hi; r += kGenThreads) {
-            Key<W> key;
-            double h;
-            if (!bad) {
-                gen_one<W>(a, L, s, r, key, h);
-            } else {
-#pragma unroll
-                for (int j = 0; j < W; ++j) key.w[j] = 0;
-                h = 0.0;
+    const int64_t obase = flat0 - a.exc_begin;  // output index of rank 0 of this source
+    const bool lds_singles = a.na * a.va <= kMaxSingles && a.nb * a.vb <= kMaxSingles;
+    if (lds_singles && !L.bad) {
+        // every single element of the source at once: h_ap + sum_{Q occ, Q != P} [(ap|qq) - d_spin (aq|qp)]
+        const int s0 = a.na * a.va, s_tot = s0 + a.nb * a.vb;
+        for (int e = tid; e < s_tot; e += kGenThreads) {
+            const int sg = e < s0 ? 0 : 1;
+            const int el = sg ? e - s0 : e;
+            const int vs = sg ? a.vb : a.va;
+            const int ip = el / vs, ia = el - ip * vs;
+            const int p = L.occ[sg][ip], t = L.vir[sg][ia];
+            double v = a.h1[t * n + p];
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int cnt = s2 ? a.nb : a.na;
+                const double *jrow = a.eri + (int64_t)(t * n + p) * n * n;
+                for (int k = 0; k < cnt; ++k) {
+                    const int q = L.occ[s2][k];
+                    if (s2 == sg && q == p) continue;
+                    const double j = jrow[q * n + q];
+                    const double kx = (s2 == sg) ? a.eri[((int64_t)(t * n + q) * n + q) * n + p] : 0.0;
+                    v += j - kx;
+                }
             }
-            const int64_t o = flat0 + r - a.exc_begin;
-            store_key<W>(a.keys, o, key);
-            a.hij[o] = h;
-            if (a.src_out) a.src_out[o] = (int32_t)src;
+            L.sval[sg][el] = v;
         }
-    } else {
-        if (bad) return;
-        const int lane = tid & (kWave - 1), wid = tid / kWave;
-        // iterate with a uniform trip count so every lane reaches the barriers
-        for (int base = r_lo; base < r_hi; base += kGenThreads) {
-            const int r = base + tid;
-            Key<W> key;
-            double h = 0.0;
-            bool keep = false;
-            if (r < r_hi) {
-                gen_one<W>(a, L, s, r, key, h);
-                keep = fabs(h) > a.eps;
+        __syncthreads();
+    }
+
+    if (L.bad) {
+        if (tid == 0) atomicOr(a.flags, SCI_FLAG_BAD_DET);
+        if constexpr (DENSE) {
+            for (int64_t r = lo + tid; r < hi; r += kGenThreads) {
+                Key<W> z;
+#pragma unroll
+                for (int j = 0; j < W; ++j) z.w[j] = 0;
+                store_key<W>(a.keys, obase + r, z);
+                a.hij[obase + r] = 0.0;
+                if (a.src_out) a.src_out[obase + r] = (int32_t)src;
             }
-            const unsigned long long m = __ballot(keep);
-            const int before = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) L.wave_tot[wid] = __popcll(m);
-            __syncthreads();
-            if (tid == 0) {
-                int tot = 0;
-                for (int w = 0; w < kGenThreads / kWave; ++w) {
-                    const int c = L.wave_tot[w];
-                    L.wave_tot[w] = tot;
-                    tot += c;
+        }
+        return;
+    }
+
+    const int Pa = a.na * (a.na - 1) / 2, Pb = a.nb * (a.nb - 1) / 2;
+    const int g1 = a.na, g2 = g1 + a.nb, g3 = g2 + Pa, g4 = g3 + Pb, n_rows = g4 + a.na * a.nb;
+    for (int g = wave; g < n_rows; g += kGenThreads / kWave) {
+        if (g < g2) {
+            // single excitations p -> a of one spin
+            const int sg = g < g1 ? 0 : 1;
+            const int ip = sg ? g - g1 : g;
+            const int R = sg ? a.vb : a.va;
+            const int64_t rb = sg ? (int64_t)a.c1 + (int64_t)ip * R : (int64_t)ip * R;
+            const int64_t t0 = lo > rb ? lo - rb : 0, t1 = hi - rb < R ? hi - rb : R;
+            if (t0 >= t1) continue;
+            const int off = sg * n;
+            const int p = (int)uni(L.occ[sg][ip]);
+            Key<W> rk = s;
+            key_flip<W>(rk, p + off);
+            rk = uni_key<W>(rk);
+            const int nocc0 = a.na, nocc1 = a.nb;
+            for (int64_t t = t0 + lane; t - lane < t1; t += kWave) {
+                const bool valid = t < t1;
+                Key<W> key = rk;
+                double h = 0.0;
+                if (valid && lds_singles) {
+                    const int ta = L.vir[sg][t];
+                    key_flip<W>(key, ta + off);
+                    const int par = L.below[sg][p] + L.below[sg][ta] - (p < ta ? 1 : 0);
+                    const double v = L.sval[sg][ip * R + (int)t];
+                    h = (par & 1) ? -v : v;
+                } else if (valid) {
+                    const int ta = L.vir[sg][t];
+                    key_flip<W>(key, ta + off);
+                    const int par = L.below[sg][p] + L.below[sg][ta] - (p < ta ? 1 : 0);
+                    // h_ap + sum over occupied Q != P of [(ap|qq) - delta_spin (aq|qp)], Q ascending
+                    double v = a.h1[ta * n + p];
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        const int cnt = s2 ? nocc1 : nocc0;
+                        for (int k = 0; k < cnt; ++k) {
+                            const int q = L.occ[s2][k];
+                            if (s2 == sg && q == p) continue;
+                            const double j = a.eri[((int64_t)(ta * n + p) * n + q) * n + q];
+                            const double kx = (s2 == sg) ? a.eri[((int64_t)(ta * n + q) * n + q) * n + p] : 0.0;
+                            v += j - kx;
+                        }
+                    }
+                    h = (par & 1) ? -v : v;
                 }
-                L.slab = tot ? atomicAdd(a.n_out, (unsigned long long)tot) : 0ull;
-                if (tot && (int64_t)(L.slab + tot) > a.capacity) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
+                emit<W, DENSE>(a, obase + rb + t, valid, key, h, src);
             }
-            __syncthreads();
-            if (keep) {
-                const int64_t o = (int64_t)L.slab + L.wave_tot[wid] + before;
-                if (o < a.capacity) {
-                    store_key<W>(a.keys, o, key);
-                    a.hij[o] = h;
-                    a.src_out[o] = (int32_t)src;
+        } else if (g < g4) {
+            // same-spin doubles p<q -> a<b
+            const int sg = g < g3 ? 0 : 1;
+            const int o = sg ? g - g3 : g - g2;
+            const int R = sg ? a.pvb : a.pva;
+            const int64_t rb = (int64_t)(sg ? a.c3 : a.c2) + (int64_t)o * R;
+            const int64_t t0 = lo > rb ? lo - rb : 0, t1 = hi - rb < R ? hi - rb : R;
+            if (t0 >= t1) continue;
+            const int off = sg * n;
+            const uint32_t po = uni(L.pocc[sg][o]);
+            const int p = (int)uni(L.occ[sg][po & 0xff]), q = (int)uni(L.occ[sg][po >> 8]);
+            const int vs = sg ? a.vb : a.va;
+            // parity bit of each particle: below(v) - [p<v] - [q<v]
+            int fb = 0;
+            if (lane < vs) {
+                const int v = L.vir[sg][lane];
+                fb = (L.below[sg][v] - (p < v) - (q < v)) & 1;
+            }
+            const uint64_t F = __ballot(fb != 0);
+            const uint32_t par0 = (uint32_t)(L.below[sg][p] + L.below[sg][q] - 1) & 1u;
+            Key<W> rk = s;
+            key_flip<W>(rk, p + off);
+            key_flip<W>(rk, q + off);
+            rk = uni_key<W>(rk);
+            const double *row = a.vanti + (int64_t)(p * n + q) * n * n;
+            for (int64_t t = t0 + lane; t - lane < t1; t += kUnroll * kWave) {
+                int ta[kUnroll], tb[kUnroll];
+                uint32_t par[kUnroll];
+                double v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t tu = t + u * kWave;
+                    ta[u] = tb[u] = 0;
+                    par[u] = 0;
+                    v[u] = 0.0;
+                    if (tu < t1) {
+                        const uint32_t pv = L.pvir[sg][tu];
+                        const int ia = pv & 0xff, ib = pv >> 8;
+                        ta[u] = L.vir[sg][ia];
+                        tb[u] = L.vir[sg][ib];
+                        par[u] = par0 ^ ((uint32_t)((F >> ia) ^ (F >> ib)) & 1u);
+                        v[u] = row[ta[u] * n + tb[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t tu = t + u * kWave;
+                    if (tu - lane >= t1) break;  // uniform: the wave's first position is past the row
+                    Key<W> key = rk;
+                    key_flip<W>(key, ta[u] + off);
+                    key_flip<W>(key, tb[u] + off);
+                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src);
                 }
             }
-            __syncthreads();
+        } else {
+            // alpha-beta doubles p(alpha) q(beta) -> a(alpha) b(beta)
+            const int o = g - g4;
+            const int ip = o / a.nb, iq = o - ip * a.nb;
+            const int R = a.va * a.vb;
+            const int64_t rb = (int64_t)a.c4 + (int64_t)o * R;
+            const int64_t t0 = lo > rb ? lo - rb : 0, t1 = hi - rb < R ? hi - rb : R;
+            if (t0 >= t1) continue;
+            const int p = (int)uni(L.occ[0][ip]), q = (int)uni(L.occ[1][iq]);
+            int fa = 0, fb = 0;
+            if (lane < a.va) {
+                const int v = L.vir[0][lane];
+                fa = (L.below[0][v] - (p < v)) & 1;
+            }
+            if (lane < a.vb) {
+                const int v = L.vir[1][lane];
+                fb = (L.below[1][v] - (q < v)) & 1;
+            }
+            const uint64_t Fa = __ballot(fa != 0), Fb = __ballot(fb != 0);
+            const uint32_t par0 = (uint32_t)(L.below[0][p] + L.below[1][q]) & 1u;
+            Key<W> rk = s;
+            key_flip<W>(rk, p);
+            key_flip<W>(rk, q + n);
+            rk = uni_key<W>(rk);
+            const double *row = a.vdir + (int64_t)(p * n + q) * n * n;
+            // particle pair of the first lane's position, then fixed strides of one wave
+            const int64_t tf = t0 + lane;
+            int ia = (int)tf / a.vb, ib = (int)tf - ((int)tf / a.vb) * a.vb;
+            const int dia = kWave / a.vb, dib = kWave - dia * a.vb;
+            for (int64_t t = tf; t - lane < t1; t += kUnroll * kWave) {
+                int ta[kUnroll], tb[kUnroll];
+                uint32_t par[kUnroll];
+                double v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t tu = t + u * kWave;
+                    ta[u] = tb[u] = 0;
+                    par[u] = 0;
+                    v[u] = 0.0;
+                    if (tu < t1) {
+                        ta[u] = L.vir[0][ia];
+                        tb[u] = L.vir[1][ib];
+                        par[u] = par0 ^ ((uint32_t)((Fa >> ia) ^ (Fb >> ib)) & 1u);
+                        v[u] = row[ta[u] * n + tb[u]];
+                    }
+                    ib += dib;
+                    ia += dia;
+                    if (ib >= a.vb) {
+                        ib -= a.vb;
+                        ++ia;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t tu = t + u * kWave;
+                    if (tu - lane >= t1) break;  // uniform: the wave's first position is past the row
+                    Key<W> key = rk;
+                    key_flip<W>(key, ta[u]);
+                    key_flip<W>(key, tb[u] + n);
+                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src);
+                }
+            }
         }
     }
 }
@@ -288,10 +417,8 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
     a.src_first = exc_begin / d.n_coupled;
     const int64_t src_last = (exc_end - 1) / d.n_coupled;
     const int64_t n_src = src_last - a.src_first + 1;
-    // split each source into near-equal chunks of at most 8192 ranks, rounded to the workgroup size
-    const int64_t chunks = ceil_div(d.n_coupled, 8192);
-    a.chunk = (int)(ceil_div(ceil_div(d.n_coupled, chunks), kGenThreads) * kGenThreads);
-    a.chunks_per_src = (int)ceil_div(d.n_coupled, a.chunk);
+    a.pva = (int)comb2(d.v_alpha);
+    a.pvb = (int)comb2(d.v_beta);
     a.exc_begin = exc_begin;
     a.exc_end = exc_end;
     a.keys = out_keys;
@@ -301,14 +428,8 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
     a.n_out = (unsigned long long *)n_out;
     a.flags = dev_flags;
     a.eps = eps;
-    a.d_va = make_fastdiv((uint32_t)d.v_alpha);
-    a.d_vb = make_fastdiv((uint32_t)d.v_beta);
-    a.d_nb = make_fastdiv((uint32_t)d.n_beta);
-    a.d_vab = make_fastdiv((uint32_t)(d.v_alpha * d.v_beta));
-    a.d_pva = make_fastdiv((uint32_t)comb2(d.v_alpha));
-    a.d_pvb = make_fastdiv((uint32_t)comb2(d.v_beta));
 
-    const int64_t grid = n_src * a.chunks_per_src;
+    const int64_t grid = n_src;
     if (grid > 0x7fffffffll) return fail(SCI_EUNSUPPORTED, "sci_gen_coupled: range too large for one launch");
     dim3 g((unsigned)grid), b(kGenThreads);
     if (d.W == 1) {
