@@ -181,6 +181,37 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
                    uint32_t *dev_flags, sci_stream_t stream);
 
 /*
+ * Streaming generation + de-duplication through a device pool (paper
+ * section 4.3: mini-batches of bounded size, reduced as they are produced;
+ * section 4.1: every batch is merged into the running unique set).
+ *
+ * The flat excitation range [exc_begin, exc_end) of `dets` (as in
+ * sci_gen_coupled) is cut into chunks of at most `chunk` candidates.  Chunk k
+ * is generated (dense mode) into pool buffer k%2 on `gen_stream`; the keys are
+ * de-duplicated and merged into the running set on `dedup_stream`, while chunk
+ * k+1 is generated into the other buffer.  The running set starts as set_in
+ * (strictly ascending, device count n_set_in) and alternates between set_a and
+ * set_b (each set_capacity keys); *final_is_b (host) tells which one holds the
+ * result, *n_set_out (device int64) its size.  H_ij values are produced into
+ * the pool and not kept.  Both streams may be the same stream.
+ *
+ * workspace   device, at least sci_stream_workspace_bytes(ham, chunk) bytes
+ *             (two pool chunks of keys + H_ij, and the dedup workspace).
+ * On overflow of set_capacity, SCI_FLAG_OVERFLOW is set and later chunks keep
+ * counting; the result is then incomplete.  The call only enqueues work; the
+ * result is ready when dedup_stream reaches the end of it.
+ * Errors: SCI_EINVAL, SCI_ECAPACITY (workspace), SCI_EHIP.
+ */
+size_t sci_stream_workspace_bytes(sci_ham_t ham, int64_t chunk);
+int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
+                         int64_t exc_begin, int64_t exc_end, int64_t chunk,
+                         const uint64_t *set_in, const int64_t *n_set_in,
+                         uint64_t *set_a, uint64_t *set_b, int64_t set_capacity,
+                         int64_t *n_set_out, int32_t *final_is_b,
+                         void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
+                         sci_stream_t gen_stream, sci_stream_t dedup_stream);
+
+/*
  * Per-kernel timing, for profiling and roofline reports (not part of the
  * method).  While enabled (process-wide), every kernel the library launches
  * is bracketed by two HIP events recorded on that kernel's stream.

@@ -58,6 +58,11 @@ _lib.sci_energy_workspace_bytes.argtypes = [_i64]
 _lib.sci_energy_workspace_bytes.restype = _sz
 _lib.sci_energy.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _P, _sz, _P, _P]
 _lib.sci_energy.restype = _i32
+_lib.sci_stream_workspace_bytes.argtypes = [_P, _i64]
+_lib.sci_stream_workspace_bytes.restype = _sz
+_lib.sci_stream_dedup.argtypes = [_P, _P, _i64, _i64, _i64, _i64, _P, _P, _P, _P, _i64, _P,
+                                  ctypes.POINTER(_i32), _P, _sz, _P, _P, _P]
+_lib.sci_stream_dedup.restype = _i32
 _lib.sci_profile_enable.argtypes = [_i32]
 _lib.sci_profile_enable.restype = _i32
 _lib.sci_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), _i32]
@@ -181,6 +186,22 @@ def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, worksp
                            _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_energy")
 
 
+def sci_stream_workspace_bytes(ham: Ham, chunk: int) -> int:
+    return int(_lib.sci_stream_workspace_bytes(ham.handle, chunk))
+
+
+def sci_stream_dedup(ham: Ham, dets, n_dets, exc_begin, exc_end, chunk, set_in, n_set_in, set_a, set_b,
+                     set_capacity, n_set_out, workspace, workspace_bytes, dev_flags, gen_stream=None,
+                     dedup_stream=None) -> bool:
+    """Returns True when the final set is set_b."""
+    fb = _i32(0)
+    _check(_lib.sci_stream_dedup(ham.handle, _ptr(dets), n_dets, exc_begin, exc_end, chunk, _ptr(set_in),
+                                 _ptr(n_set_in), _ptr(set_a), _ptr(set_b), set_capacity, _ptr(n_set_out),
+                                 ctypes.byref(fb), _ptr(workspace), workspace_bytes, _ptr(dev_flags),
+                                 _stream(gen_stream), _stream(dedup_stream)), "sci_stream_dedup")
+    return bool(fb.value)
+
+
 # ---------------------------------------------------------------------------
 # allocating conveniences
 # ---------------------------------------------------------------------------
@@ -266,6 +287,26 @@ def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_
         flags = new_flags(dev)
     sci_energy(ham, sel, n, psi, e, hp, g, workspace, workspace.numel(), flags)
     return e, hp, g, flags
+
+
+def stream_dedup(ham: Ham, dets: torch.Tensor, chunk: int, set_in: torch.Tensor, set_capacity: int,
+                 exc_begin=0, exc_end=None, gen_stream=None, dedup_stream=None, flags=None):
+    """Streamed generation + dedup-merge of all coupled determinants of `dets` into `set_in`."""
+    dev = dets.device
+    n = dets.shape[0]
+    if exc_end is None:
+        exc_end = n * ham.n_coupled
+    W = ham.W
+    set_a = torch.empty((max(set_capacity, 1), W), dtype=torch.int64, device=dev)
+    set_b = torch.empty_like(set_a)
+    n_in = torch.tensor([set_in.shape[0]], dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(sci_stream_workspace_bytes(ham, chunk), 1), dtype=torch.uint8, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    is_b = sci_stream_dedup(ham, dets, n, exc_begin, exc_end, chunk, set_in, n_in, set_a, set_b, set_capacity, n_out,
+                            ws, ws.numel(), flags, gen_stream, dedup_stream)
+    return (set_b if is_b else set_a), n_out, flags
 
 
 class SciEnergy(torch.autograd.Function):

@@ -492,10 +492,26 @@ __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
     const int64_t *cp = a.counts + a.cbase[s];
     for (int j = threadIdx.x; j < f; j += kDThreads) s_run[j] = (unsigned long long)cp[(int64_t)j * T + t];
     __syncthreads();
-    for (int64_t i = start + threadIdx.x; i < end; i += kDThreads) {
-        const int b = a.ids[i];
-        const unsigned long long pos = atomicAdd(&s_run[b], 1ull);
-        store_key<W>(a.out, (int64_t)pos, load_key<W>(a.in, i));
+    constexpr int U = 8;
+    for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kDThreads) {
+        Key<W> k[U];
+        int b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            b[u] = -1;
+            if (i < end) {
+                b[u] = a.ids[i];
+                k[u] = load_key<W>(a.in, i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b[u] >= 0) {
+                const unsigned long long pos = atomicAdd(&s_run[b[u]], 1ull);
+                store_key<W>(a.out, (int64_t)pos, k[u]);
+            }
+        }
     }
 }
 
@@ -734,7 +750,20 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     }
     if (size > 0) {
         const int m = (int)size;
-        for (int i = threadIdx.x; i < m; i += kDThreads) s_k0[i] = load_key<W>(a.src, start + i);
+        {
+            // every load in flight before the first LDS store
+            Key<W> tmp[C::K];
+#pragma unroll
+            for (int k = 0; k < C::K; ++k) {
+                const int i = k * kDThreads + threadIdx.x;
+                if (i < m) tmp[k] = load_key<W>(a.src, start + i);
+            }
+#pragma unroll
+            for (int k = 0; k < C::K; ++k) {
+                const int i = k * kDThreads + threadIdx.x;
+                if (i < m) s_k0[i] = tmp[k];
+            }
+        }
         // hash table of 16-bit key indices (0xffff = empty), two slots per 32-bit word
         int T = 16;
         while (T < 2 * m) T <<= 1;
@@ -937,10 +966,22 @@ __global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
     int64_t ou = a.uoff[s], on = a.noff[s];
     if (nBs == 0) {
         // common case: the run is the union and all of it is novel
-        for (int64_t i = threadIdx.x; i < nA; i += kDThreads) {
-            const Key<W> k = load_key<W>(A, i);
-            if (ou + i < a.out_cap) store_key<W>(a.out, ou + i, k);
-            if (a.novel && on + i < a.novel_cap) store_key<W>(a.novel, on + i, k);
+        constexpr int U = 8;
+        for (int64_t i0 = 0; i0 < nA; i0 += (int64_t)U * kDThreads) {
+            Key<W> k[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + u * kDThreads + threadIdx.x;
+                if (i < nA) k[u] = load_key<W>(A, i);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + u * kDThreads + threadIdx.x;
+                if (i < nA) {
+                    if (ou + i < a.out_cap) store_key<W>(a.out, ou + i, k[u]);
+                    if (a.novel && on + i < a.novel_cap) store_key<W>(a.novel, on + i, k[u]);
+                }
+            }
         }
         return;
     }

@@ -29,6 +29,7 @@ struct EnergyArgs {
     const double *psi;
     double *hpsi;      // [n_sel]
     double *partial;   // [2][n_blocks]
+    double *partial_rows;  // [n_col][n_sel] off-diagonal partial row sums
     double *scalars;   // [2]: numerator, denominator
     double *energy;    // [1]
     double *grad;      // nullable [n_sel]
@@ -133,6 +134,9 @@ __device__ double diag_elem(const EnergyArgs &a, const Key<W> &d) {
     return e1 + e2;
 }
 
+// Off-diagonal part of (H psi)_i for the rows of blockIdx.x against the
+// columns of column block blockIdx.y; the partial sum goes to
+// partial_rows[blockIdx.y][i] (combined in a fixed order by hpsi_finish_kernel).
 template <int W>
 __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
     __shared__ Key<W> tile_keys[kColTile];
@@ -146,17 +150,40 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
     double acc = 0.0;
     if (active) {
         di = load_key<W>(a.sel, i);
-        int na, nb;
-        spin_popc<W>(di, a.n, na, nb);
-        if (na != a.na || nb != a.nb || key_popc<W>(di) != na + nb) atomicOr(a.flags, SCI_FLAG_BAD_DET);
-        if (i + 1 < a.n_sel && !key_less<W>(di, load_key<W>(a.sel, i + 1))) atomicOr(a.flags, SCI_FLAG_UNSORTED);
+        if (blockIdx.y == 0) {
+            int na, nb;
+            spin_popc<W>(di, a.n, na, nb);
+            if (na != a.na || nb != a.nb || key_popc<W>(di) != na + nb) atomicOr(a.flags, SCI_FLAG_BAD_DET);
+            if (i + 1 < a.n_sel && !key_less<W>(di, load_key<W>(a.sel, i + 1)))
+                atomicOr(a.flags, SCI_FLAG_UNSORTED);
+        }
     }
-    for (int64_t j0 = 0; j0 < a.n_sel; j0 += kColTile) {
-        const int cnt = (int)min<int64_t>(kColTile, a.n_sel - j0);
+    const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)gridDim.y), (int64_t)kColTile) * kColTile;
+    const int64_t c0 = (int64_t)blockIdx.y * per;
+    const int64_t c1 = min<int64_t>(c0 + per, a.n_sel);
+    for (int64_t j0 = c0; j0 < c1; j0 += kColTile) {
+        const int cnt = (int)min<int64_t>(kColTile, c1 - j0);
         __syncthreads();
-        for (int t = tid; t < cnt; t += kRowThreads) {
-            tile_keys[t] = load_key<W>(a.sel, j0 + t);
-            tile_psi[t] = a.psi[j0 + t];
+        {
+            constexpr int U = kColTile / kRowThreads;
+            Key<W> kt[U];
+            double pt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = u * kRowThreads + tid;
+                if (t < cnt) {
+                    kt[u] = load_key<W>(a.sel, j0 + t);
+                    pt[u] = a.psi[j0 + t];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = u * kRowThreads + tid;
+                if (t < cnt) {
+                    tile_keys[t] = kt[u];
+                    tile_psi[t] = pt[u];
+                }
+            }
         }
         __syncthreads();
         if (active) {
@@ -170,10 +197,18 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
             }
         }
     }
-    if (active) {
-        const double hii = diag_elem<W>(a, di);
-        a.hpsi[i] = hii * a.psi[i] + acc;
-    }
+    if (active) a.partial_rows[(int64_t)blockIdx.y * a.n_sel + i] = acc;
+}
+
+// (H psi)_i = H_ii psi_i + the column-block partial sums in block order
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_finish_kernel(EnergyArgs a, int n_col) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= a.n_sel) return;
+    double acc = 0.0;
+    for (int c = 0; c < n_col; ++c) acc += a.partial_rows[(int64_t)c * a.n_sel + i];
+    const Key<W> di = load_key<W>(a.sel, i);
+    a.hpsi[i] = diag_elem<W>(a, di) * a.psi[i] + acc;
 }
 
 // per-block partial sums of psi_i*(H psi)_i and psi_i^2, fixed tree order
@@ -241,9 +276,14 @@ __global__ void grad_kernel(EnergyArgs a) {
 
 static int64_t reduce_blocks(int64_t n_sel) { return std::max<int64_t>(1, ceil_div(n_sel, (int64_t)kRedThreads * 8)); }
 
+constexpr int kColSplit = 8;  // column blocks per row block (more workgroups in flight)
+
+static int col_split(int64_t n_sel) { return n_sel >= (int64_t)kColSplit * kColTile ? kColSplit : 1; }
+
 static size_t energy_ws(int64_t n_sel) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16);
+    return al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16) +
+           al((size_t)col_split(n_sel) * n_sel * 8);
 }
 
 }  // namespace sci
@@ -287,13 +327,20 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
     a.hpsi = h_psi ? h_psi : (double *)ws;
     a.partial = (double *)(ws + al((size_t)n_sel * 8));
     a.scalars = (double *)(ws + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16));
+    a.partial_rows = (double *)(ws + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16));
     a.energy = energy;
     a.grad = grad;
     a.flags = dev_flags;
 
     const int64_t row_blocks = ceil_div(n_sel, kRowThreads);
-    if (d.W == 1) SCI_LAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
-    else SCI_LAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a);
+    const int nc = col_split(n_sel);
+    if (d.W == 1) {
+        SCI_LAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+        SCI_LAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+    } else {
+        SCI_LAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+        SCI_LAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+    }
     SCI_HIP_TRY(hipGetLastError());
     const int64_t nb = reduce_blocks(n_sel);
     SCI_LAUNCH(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);

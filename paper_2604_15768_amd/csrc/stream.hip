@@ -1,0 +1,120 @@
+// Pool streaming: chunked generation feeding de-duplication (paper section
+// 4.3, mini-batch execution; section 4.1, merge into the unique set).
+//
+// Two pool buffers hold consecutive chunks of candidates.  Generation of chunk
+// k+1 (gen stream) overlaps the de-duplication and merge of chunk k (dedup
+// stream); events order each buffer's reuse.  Set sizes never leave the
+// device, so the loop needs no host synchronisation.
+#include <vector>
+
+#include "sci_internal.hpp"
+
+namespace sci {
+
+struct StreamLayout {
+    size_t keys[2], hij[2], dedup, n_gen, total;
+};
+
+static size_t al256s(size_t b) { return (b + 255) / 256 * 256; }
+
+static StreamLayout stream_layout(int W, int64_t chunk) {
+    StreamLayout L{};
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b) {
+        L.keys[b] = off;
+        off += al256s((size_t)chunk * W * 8);
+        L.hij[b] = off;
+        off += al256s((size_t)chunk * 8);
+    }
+    L.n_gen = off;
+    off += 256;
+    L.dedup = off;
+    off += sci_dedup_workspace_bytes(W, chunk);
+    L.total = off;
+    return L;
+}
+
+}  // namespace sci
+
+using namespace sci;
+
+extern "C" size_t sci_stream_workspace_bytes(sci_ham_t ham, int64_t chunk) {
+    if (!ham || chunk < 1) return 0;
+    return stream_layout(ham->dev.W, chunk).total;
+}
+
+extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t n_dets, int64_t exc_begin,
+                                    int64_t exc_end, int64_t chunk, const uint64_t *set_in, const int64_t *n_set_in,
+                                    uint64_t *set_a, uint64_t *set_b, int64_t set_capacity, int64_t *n_set_out,
+                                    int32_t *final_is_b, void *workspace, size_t workspace_bytes,
+                                    uint32_t *dev_flags, sci_stream_t gen_stream, sci_stream_t dedup_stream) {
+    set_error("");
+    if (!ham) return fail(SCI_EINVAL, "sci_stream_dedup: NULL handle");
+    const int W = ham->dev.W;
+    if (chunk < 1) return fail(SCI_EINVAL, "sci_stream_dedup: chunk must be >= 1");
+    if (!set_a || !set_b || set_a == set_b || !n_set_out || !final_is_b || !workspace || !dev_flags)
+        return fail(SCI_EINVAL, "sci_stream_dedup: NULL or aliased argument");
+    if (set_in && !n_set_in) return fail(SCI_EINVAL, "sci_stream_dedup: set_in without n_set_in");
+    if (set_in == set_a || set_in == set_b) return fail(SCI_EINVAL, "sci_stream_dedup: set_in aliases an output set");
+    if (n_dets < 0 || exc_begin < 0 || exc_end < exc_begin || exc_end > n_dets * ham->dev.n_coupled)
+        return fail(SCI_EINVAL, "sci_stream_dedup: bad excitation range");
+    const StreamLayout L = stream_layout(W, chunk);
+    if (workspace_bytes < L.total)
+        return fail(SCI_ECAPACITY, "sci_stream_dedup: workspace %zu < %zu bytes", workspace_bytes, L.total);
+    hipStream_t sg = (hipStream_t)gen_stream, sd = (hipStream_t)dedup_stream;
+    char *ws = (char *)workspace;
+    const int64_t n_chunks = exc_end > exc_begin ? ceil_div(exc_end - exc_begin, chunk) : 0;
+
+    // ready[b]: buffer b consumed by the dedup stream; filled[b]: buffer b generated
+    hipEvent_t ready[2] = {nullptr, nullptr}, filled[2] = {nullptr, nullptr};
+    for (int b = 0; b < 2; ++b) {
+        SCI_HIP_TRY(hipEventCreateWithFlags(&ready[b], hipEventDisableTiming));
+        SCI_HIP_TRY(hipEventCreateWithFlags(&filled[b], hipEventDisableTiming));
+    }
+    auto cleanup = [&]() {
+        for (int b = 0; b < 2; ++b) {
+            if (ready[b]) (void)hipEventDestroy(ready[b]);
+            if (filled[b]) (void)hipEventDestroy(filled[b]);
+        }
+    };
+
+    const uint64_t *cur_set = set_in;
+    const int64_t *cur_n = set_in ? n_set_in : nullptr;
+    int out_b = 0;  // next output set: 0 -> set_a, 1 -> set_b
+    int32_t st = SCI_OK;
+    if (n_chunks == 0) {
+        // nothing to generate: the result is the input set
+        st = sci_dedup_merge(W, nullptr, 0, cur_set, cur_n, set_a, n_set_out, set_capacity, nullptr, nullptr, 0,
+                             ws + L.dedup, workspace_bytes - L.dedup, dev_flags, dedup_stream);
+        *final_is_b = 0;
+        cleanup();
+        return st;
+    }
+    // the dedup stream must not start before work already queued on the gen stream (inputs)
+    SCI_HIP_TRY(hipEventRecord(filled[1], sg));
+    SCI_HIP_TRY(hipStreamWaitEvent(sd, filled[1], 0));
+    for (int64_t k = 0; k < n_chunks; ++k) {
+        const int b = (int)(k & 1);
+        const int64_t e0 = exc_begin + k * chunk;
+        const int64_t e1 = e0 + chunk < exc_end ? e0 + chunk : exc_end;
+        if (k >= 2) SCI_HIP_TRY(hipStreamWaitEvent(sg, ready[b], 0));  // buffer b free again
+        st = sci_gen_coupled(ham, dets, n_dets, e0, e1, -1.0, (uint64_t *)(ws + L.keys[b]), (double *)(ws + L.hij[b]),
+                             nullptr, chunk, (int64_t *)(ws + L.n_gen), dev_flags, gen_stream);
+        if (st != SCI_OK) break;
+        SCI_HIP_TRY(hipEventRecord(filled[b], sg));
+        SCI_HIP_TRY(hipStreamWaitEvent(sd, filled[b], 0));
+        uint64_t *dst = out_b ? set_b : set_a;
+        // the set written two chunks ago is being read now; the running count lives in n_set_out
+        st = sci_dedup_merge(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
+                             set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup, dev_flags,
+                             dedup_stream);
+        if (st != SCI_OK) break;
+        SCI_HIP_TRY(hipEventRecord(ready[b], sd));
+        cur_set = dst;
+        cur_n = n_set_out;
+        out_b ^= 1;
+    }
+    *final_is_b = out_b ^ 1;
+    cleanup();
+    return st;
+}

@@ -337,3 +337,33 @@ def test_dedup_streamed_chunks(W):
     u0, _ = oracle.dedup_merge(W, c0, empty)
     _dedup_check(sci, c0, empty, W)
     _dedup_check(sci, c1, u0, W)
+
+
+@pytest.mark.parametrize("name,n_src,chunk", [("tiny", None, 1000), ("medium", 300, 1_000_003), ("large", 24, 3_000_000)])
+def test_stream_dedup_matches_oracle(name, n_src, chunk):
+    """Pool streaming (generation of chunk k+1 overlapping dedup of chunk k on a second
+    stream) equals the oracle's union of every coupled set with the selected set."""
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    dets = s.dets if n_src is None else s.dets[pick_sources(s.dets.shape[0], n_src, 31)]
+    d = sci.keys_to_device(dets)
+    sel = sci.keys_to_device(s.dets)
+    total = dets.shape[0] * h.n_coupled
+    say(f"stream dedup {name}: {total} candidates in chunks of {chunk}")
+    side = torch.cuda.Stream()
+    out, n_out, flags = sci.stream_dedup(h, d, chunk, sel, total + s.dets.shape[0], dedup_stream=side)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "stream") == 0
+    ok, _, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
+    ou, _ = oracle.dedup_merge(s.W, ok, s.dets)
+    n = int(n_out.item())
+    assert n == ou.shape[0]
+    assert np.array_equal(sci.keys_to_host(out[:n]), ou)
+    # a sub-range of the excitation space, including partial first and last sources
+    a0, a1 = h.n_coupled // 3, total - h.n_coupled // 5
+    out2, n2, _ = sci.stream_dedup(h, d, chunk, sel, total + s.dets.shape[0], exc_begin=a0, exc_end=a1)
+    torch.cuda.synchronize()
+    ou2, _ = oracle.dedup_merge(s.W, ok[a0:a1], s.dets)
+    assert int(n2.item()) == ou2.shape[0]
+    assert np.array_equal(sci.keys_to_host(out2[:int(n2.item())]), ou2)
