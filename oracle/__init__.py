@@ -70,6 +70,8 @@ def _load():
         lib.ora_energy.restype = i32
         lib.ora_hpsi_rows.argtypes = [i32, i32, i32, i32, P, P, P, i64, P, P, i64, P]
         lib.ora_hpsi_rows.restype = i32
+        lib.ora_dense_h.argtypes = [i32, i32, i32, i32, P, P, P, i64, P]
+        lib.ora_dense_h.restype = i32
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = i32
         _lib = lib
@@ -89,7 +91,7 @@ class use_library:
         self._saved = _lib
         lib = ctypes.CDLL(self.path)
         for fn in ("ora_literal_row", "ora_n_coupled", "ora_diag", "ora_gen_coupled", "ora_dedup_merge",
-                   "ora_energy", "ora_hpsi_rows", "ora_num_threads"):
+                   "ora_energy", "ora_hpsi_rows", "ora_dense_h", "ora_num_threads"):
             src = getattr(self._saved, fn)
             dst = getattr(lib, fn)
             dst.argtypes = src.argtypes
@@ -265,16 +267,13 @@ def dense_h_literal(n_orb, n_alpha, n_beta, h1, eri, basis):
 
 
 def dense_h_sc(n_orb, n_alpha, n_beta, h1, eri, basis):
-    """Dense <i|H|j> on `basis` from the Slater–Condon tier (diag + coupled rows)."""
-    idx = _index_of(basis)
+    """Dense <i|H|j> on `basis` (strictly ascending) from the Slater–Condon tier."""
+    W = words(n_orb)
+    h1, eri = _ham(h1, eri)
+    basis = _dets(basis, W)
     n = basis.shape[0]
-    nc = n_coupled(n_orb, n_alpha, n_beta)
-    keys, hij, _ = gen_coupled(n_orb, n_alpha, n_beta, h1, eri, basis)
-    hm = np.zeros((n, n))
-    for j in range(n):
-        hm[j, j] = diag(n_orb, n_alpha, n_beta, h1, eri, basis[j])
-        for r in range(nc):
-            i = idx.get(tuple(int(x) for x in keys[j * nc + r]))
-            if i is not None:
-                hm[i, j] = hij[j * nc + r]
-    return hm
+    out = np.zeros((n, n))
+    rc = _load().ora_dense_h(n_orb, n_alpha, n_beta, W, _p(h1), _p(eri), _p(basis), n, _p(out))
+    if rc != 0:
+        raise ValueError("oracle dense_h failed (%d)" % rc)
+    return np.ascontiguousarray(out.T)  # out[j, i] = <i|H|j>

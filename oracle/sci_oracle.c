@@ -568,6 +568,42 @@ int ora_hpsi_rows(int n_orb, int n_alpha, int n_beta, int W,
     return bad ? -2 : 0;
 }
 
+/*
+ * Dense <b_i|H|b_j> on a strictly ascending basis (column-major by source j:
+ * out[j*n + i]).  Column j holds H_jj and every coupled determinant of b_j
+ * that lies in the basis.  Returns 0, -1 (unsorted), -2 (invalid determinant).
+ */
+int ora_dense_h(int n_orb, int n_alpha, int n_beta, int W,
+                const double *h, const double *eri,
+                const uint64_t *basis, int64_t n, double *out)
+{
+    ora_ham H = {n_orb, n_alpha, n_beta, W, h, eri};
+    for (int64_t i = 1; i < n; ++i)
+        if (key_cmp(basis + (i - 1) * W, basis + i * W, W) >= 0) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (!det_valid(&H, basis + i * W)) return -2;
+    int64_t nc = ora_n_coupled(n_orb, n_alpha, n_beta);
+    memset(out, 0, (size_t)n * n * sizeof(double));
+#pragma omp parallel
+    {
+        uint64_t *kb = (uint64_t *)malloc((size_t)(nc ? nc : 1) * W * 8);
+        double *hb = (double *)malloc((size_t)(nc ? nc : 1) * 8);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t j = 0; j < n; ++j) {
+            const uint64_t *d = basis + j * W;
+            out[j * n + j] = diag_elem(&H, d);
+            gen_one(&H, d, kb, hb);
+            for (int64_t r = 0; r < nc; ++r) {
+                int64_t i = find_key(basis, n, W, kb + r * W);
+                if (i >= 0) out[j * n + i] = hb[r];
+            }
+        }
+        free(kb);
+        free(hb);
+    }
+    return 0;
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

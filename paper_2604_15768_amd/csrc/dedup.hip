@@ -699,22 +699,18 @@ struct BucketLds {
     int64_t red[kDWaves];
 };
 
-// 64-bit finaliser mix (multiply / xor-shift) of a key, for the LDS hash table
+// Multiplicative hash of a key to log2(T) bits (keys of one bucket differ mostly in low bits).
 template <int W>
-__device__ __forceinline__ uint32_t key_hash(const Key<W> &k) {
+__device__ __forceinline__ uint32_t key_hash(const Key<W> &k, int log_t) {
     uint64_t x = k.w[0];
 #pragma unroll
-    for (int j = 1; j < W; ++j) x ^= (k.w[j] << 29) | (k.w[j] >> 35);
-    x ^= x >> 33;
-    x *= 0xff51afd7ed558ccdull;
-    x ^= x >> 33;
-    x *= 0xc4ceb9fe1a85ec53ull;
-    x ^= x >> 33;
-    return (uint32_t)x;
+    for (int j = 1; j < W; ++j) x ^= k.w[j] * 0x9E3779B97F4A7C15ull;
+    const uint32_t y = (uint32_t)x ^ (uint32_t)(x >> 32) * 0x85EBCA6Bu;
+    return (y * 0x9E3779B1u) >> (32 - log_t);
 }
 
-// Rank one digit per lane within the wave (as wave_match_rank), skipping digit
-// bits on which every active lane agrees (uniform ballots need no vector work).
+// Rank one digit per lane within the wave, skipping digit bits on which every
+// active lane agrees (uniform ballots need no vector work).
 __device__ __forceinline__ int wave_match_rank_skip(uint32_t d, bool valid, int *rank) {
     const uint64_t act = __ballot(valid);
     uint64_t same = act;
@@ -727,13 +723,39 @@ __device__ __forceinline__ int wave_match_rank_skip(uint32_t d, bool valid, int 
     return __popcll(same);
 }
 
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+    for (int o = 1; o < kWave; o <<= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+// Wave-level exclusive scan of 256 digit totals held 4 per lane; returns the
+// prefix of digit 4*lane+j in pre[j].
+__device__ __forceinline__ void wave_scan256(const uint32_t tot[4], uint32_t pre[4]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t s = tot[0] + tot[1] + tot[2] + tot[3];
+    uint32_t x = s;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    uint32_t run = x - s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        pre[j] = run;
+        run += tot[j];
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
-    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then the unique keys
+    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
     __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
     __shared__ uint16_t s_rank[C::CAP];      // per-key rank within its wave and digit
-    __shared__ BucketLds L;
+    __shared__ uint32_t s_cnt[kDWaves][256]; // per-wave digit counts, then that wave's output offsets
+    __shared__ uint64_t s_or[2];
+    __shared__ int s_u[kDWaves];
+    __shared__ int64_t s_wsum[kDWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t s = blockIdx.x;
     const int64_t start = a.seg[s], size = a.seg[s + 1] - a.seg[s];
@@ -750,6 +772,10 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     }
     if (size > 0) {
         const int m = (int)size;
+        // each wave owns a contiguous slice of CHm positions
+        const int Km = (m + kDThreads - 1) / kDThreads;
+        const int CHm = Km * kWave;
+        const int my0 = w * CHm;
         {
             // every load in flight before the first LDS store
             Key<W> tmp[C::K];
@@ -765,19 +791,21 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
             }
         }
         // hash table of 16-bit key indices (0xffff = empty), two slots per 32-bit word
-        int T = 16;
-        while (T < 2 * m) T <<= 1;
+        int log_t = 4;
+        while ((1 << log_t) < 2 * m) ++log_t;
+        const uint32_t tmask = (1u << log_t) - 1u;
         uint32_t *tab = reinterpret_cast<uint32_t *>(s_k1);
-        for (int i = threadIdx.x; i < T / 2; i += kDThreads) tab[i] = 0xffffffffu;
+        for (int i = threadIdx.x; i < (1 << log_t) / 2; i += kDThreads) tab[i] = 0xffffffffu;
+        if (threadIdx.x == 0) s_or[0] = s_or[1] = 0;
         __syncthreads();
-        // one round = 256 consecutive keys; bit r of `fresh` marks a first occurrence in round r
+        const Key<W> ref = s_k0[0];
+        // bit k of `fresh`: this lane's key of round k is the first occurrence of its value
         uint32_t fresh = 0;
-        const int rounds = (m + kDThreads - 1) / kDThreads;
-        for (int r = 0; r < rounds; ++r) {
-            const int i = r * kDThreads + threadIdx.x;
+        for (int k = 0; k < Km; ++k) {
+            const int i = my0 + k * kWave + lane;
             if (i >= m) continue;
             const Key<W> key = s_k0[i];
-            uint32_t h = key_hash<W>(key) & (uint32_t)(T - 1);
+            uint32_t h = key_hash<W>(key, log_t);
             while (true) {
                 const uint32_t cur = tab[h >> 1];
                 const uint32_t v = (h & 1u) ? (cur >> 16) : (cur & 0xffffu);
@@ -785,78 +813,117 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
                     const uint32_t want = (h & 1u) ? ((cur & 0xffffu) | ((uint32_t)i << 16))
                                                    : ((cur & 0xffff0000u) | (uint32_t)i);
                     if (atomicCAS(&tab[h >> 1], cur, want) == cur) {
-                        fresh |= 1u << r;
+                        fresh |= 1u << k;
                         break;
                     }
                     continue;  // the word changed: look at this slot again
                 }
                 if (key_eq<W>(s_k0[v], key)) break;  // seen before
-                h = (h + 1u) & (uint32_t)(T - 1);
+                h = (h + 1u) & tmask;
             }
         }
-        __syncthreads();
-        // compact the first occurrences to the front of s_k0 (in place, round by round)
-        const Key<W> ref = s_k0[0];
+        __syncthreads();  // all probes done: keys may move
+        // each wave compacts its first occurrences to the front of its own slice
+        int uw = 0;
         uint64_t acc[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) acc[j] = 0;
-        int u = 0;
-        for (int r = 0; r < rounds; ++r) {
-            const int i = r * kDThreads + threadIdx.x;
-            const bool keep = (i < m) && ((fresh >> r) & 1u);
+        for (int k = 0; k < Km; ++k) {
+            const int i = my0 + k * kWave + lane;
+            const bool keep = (i < m) && ((fresh >> k) & 1u);
             Key<W> key;
             if (keep) {
                 key = s_k0[i];
 #pragma unroll
                 for (int j = 0; j < W; ++j) acc[j] |= key.w[j] ^ ref.w[j];
             }
-            int64_t tot;
-            const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, L.R.wsum);  // reads of the round end here
-            if (keep) s_k0[u + ex] = key;
-            u += (int)tot;
+            const uint64_t bal = __ballot(keep);
+            if (keep) s_k0[my0 + uw + __popcll(bal & lanemask_lt())] = key;
+            uw += __popcll(bal);
         }
-        if (threadIdx.x == 0) L.R.orx[0] = L.R.orx[1] = 0;
-        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < W; ++j)
-            if (acc[j]) atomicOr((unsigned long long *)&L.R.orx[j], (unsigned long long)acc[j]);
+        for (int j = 0; j < W; ++j) {
+            const uint64_t o = wave_or64(acc[j]);
+            if (lane == 0 && o) atomicOr((unsigned long long *)&s_or[j], (unsigned long long)o);
+        }
+        if (lane == 0) s_u[w] = uw;
         __syncthreads();
-        uint64_t o[W];
+        uint64_t orx[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j) o[j] = L.R.orx[j];
-        const int nbits = varying_bits<W>(o);
+        for (int j = 0; j < W; ++j) orx[j] = s_or[j];
+        const int nbits = varying_bits<W>(orx);
+        int u = 0;
+#pragma unroll
+        for (int ww = 0; ww < kDWaves; ++ww) u += s_u[ww];
 
-        // stable LSD radix sort of the u unique keys, LDS resident
+        // stable LSD radix sort of the u unique keys, LDS resident.  The first pass
+        // reads every wave's own slice (any starting order is fine); later passes
+        // read the contiguous result of the previous pass.
         Key<W> *cur = s_k0, *nxt = s_k1;
         const int Kd = (u + kDThreads - 1) / kDThreads;
         const int CHd = Kd * kWave;
+        bool first = true;
         for (int shift = 0; shift < nbits; shift += 8) {
-            for (int d = lane; d < 256; d += kWave) L.R.cnt[w][d] = 0;
-            for (int k = 0; k < Kd; ++k) {
-                const int pos = w * CHd + k * kWave + lane;
-                const bool valid = pos < u;
+            const int base_pos = first ? my0 : w * CHd;
+            const int rounds = first ? Km : Kd;
+            const int limit = first ? my0 + uw : u;
+            for (int d = lane; d < 256; d += kWave) s_cnt[w][d] = 0;
+            for (int k = 0; k < rounds; ++k) {
+                const int pos = base_pos + k * kWave + lane;
+                const bool valid = pos < limit;
                 const uint32_t d = valid ? digit_of<W>(cur[pos], shift) : 0u;
                 int rk;
                 const int tot = wave_match_rank_skip(d, valid, &rk);
                 uint32_t base = 0;
-                if (valid) base = L.R.cnt[w][d];
-                if (valid && rk == 0) L.R.cnt[w][d] = base + (uint32_t)tot;
+                if (valid) base = s_cnt[w][d];
+                if (valid && rk == 0) s_cnt[w][d] = base + (uint32_t)tot;
                 if (valid) s_rank[pos] = (uint16_t)(base + (uint32_t)rk);
             }
             __syncthreads();
-            radix_offsets(L.R, nullptr);
-            __syncthreads();
-            for (int k = 0; k < Kd; ++k) {
-                const int pos = w * CHd + k * kWave + lane;
-                if (pos < u) {
+            // this wave's output offset per digit: all keys of smaller digits, plus
+            // keys of this digit held by lower waves (each wave computes its own row)
+            uint32_t tot[4], pre[4], low[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int d = 4 * lane + j;
+                uint32_t t = 0, l = 0;
+#pragma unroll
+                for (int ww = 0; ww < kDWaves; ++ww) {
+                    const uint32_t c = s_cnt[ww][d];
+                    t += c;
+                    l += (ww < w) ? c : 0u;
+                }
+                tot[j] = t;
+                low[j] = l;
+            }
+            wave_scan256(tot, pre);
+            __syncthreads();  // every wave has read the counts before rows are overwritten
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s_cnt[w][4 * lane + j] = pre[j] + low[j];
+            for (int k = 0; k < rounds; ++k) {
+                const int pos = base_pos + k * kWave + lane;
+                if (pos < limit) {
                     const Key<W> key = cur[pos];
-                    nxt[L.R.cnt[w][digit_of<W>(key, shift)] + s_rank[pos]] = key;
+                    nxt[s_cnt[w][digit_of<W>(key, shift)] + s_rank[pos]] = key;
                 }
             }
             __syncthreads();
             Key<W> *t = cur;
             cur = nxt;
             nxt = t;
+            first = false;
+        }
+        if (first) {
+            // no pass ran: every unique key is equal, so there is exactly one
+            if (threadIdx.x == 0) {
+                for (int ww = 0; ww < kDWaves; ++ww)
+                    if (s_u[ww] > 0) {
+                        s_k1[0] = s_k0[ww * CHm];
+                        break;
+                    }
+            }
+            __syncthreads();
+            cur = s_k1;
         }
         // the sorted unique run to the bucket's offset; set hits for the union count
         int64_t hit = 0;
@@ -866,9 +933,11 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
             if (bh > bl && contains_set<W>(a.B, bl, bh, key)) ++hit;
         }
         nu = u;
-        int64_t ht;
-        block_excl_scan_i64(hit, &ht, L.R.wsum);
-        matches = ht;
+        if (bh > bl) {
+            int64_t ht;
+            block_excl_scan_i64(hit, &ht, s_wsum);
+            matches = ht;
+        }
     }
     if (threadIdx.x == 0) {
         a.nuniq[s] = nu;
