@@ -433,13 +433,18 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
     const int64_t start = a.seg_in[s] + t * a.tile;
     const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
     const uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
-    for (int j = threadIdx.x; j < f - 1; j += kDThreads) s_spl[j] = load_key<W>(sp, j);
+    // splitters padded to FMAX-1 with the all-ones key, which no key is above: every
+    // search below takes exactly log2(FMAX) steps with no bounds checks
+    for (int j = threadIdx.x; j < FMAX - 1; j += kDThreads) {
+        if (j < f - 1) s_spl[j] = load_key<W>(sp, j);
+        else {
+#pragma unroll
+            for (int q = 0; q < W; ++q) s_spl[j].w[q] = ~0ull;
+        }
+    }
     for (int j = threadIdx.x; j < f; j += kDThreads) s_cnt[j] = 0;
     __syncthreads();
-    // four keys per thread in flight: independent fixed-trip searches hide LDS latency
-    const int nspl = f - 1;
-    int top = 1;
-    while (top * 2 <= nspl) top *= 2;
+    constexpr int kSteps = __builtin_ctz(FMAX);
     for (int64_t i0 = start; i0 < end; i0 += 4 * kDThreads) {
         Key<W> k[4];
         int pos[4];
@@ -455,13 +460,13 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
             }
             pos[u] = 0;
         }
-        if (nspl > 0) {
-            for (int step = top; step > 0; step >>= 1) {
+        // branch-free lower bound: pos = number of splitters below the key
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int nxt = pos[u] + step;
-                    if (nxt <= nspl && key_less<W>(s_spl[nxt - 1], k[u])) pos[u] = nxt;
-                }
+        for (int st = kSteps - 1; st >= 0; --st) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int nxt = pos[u] + (1 << st);
+                if (key_less<W>(s_spl[nxt - 1], k[u])) pos[u] = nxt;
             }
         }
 #pragma unroll
