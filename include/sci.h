@@ -197,9 +197,12 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
  *
  * workspace   device, at least sci_stream_workspace_bytes(ham, chunk) bytes
  *             (two pool chunks of keys + H_ij, and the dedup workspace).
- * On overflow of set_capacity, SCI_FLAG_OVERFLOW is set and later chunks keep
- * counting; the result is then incomplete.  The call only enqueues work; the
- * result is ready when dedup_stream reaches the end of it.
+ * On overflow of set_capacity, SCI_FLAG_OVERFLOW is set and the running set
+ * keeps only the first set_capacity keys of the sorted union; later chunks
+ * merge into that truncated set (never reading past set_capacity keys), so the
+ * final set is incomplete and *n_set_out is then a lower bound on the size the
+ * complete union needs.  The call only enqueues work; the result is ready when
+ * dedup_stream reaches the end of it.
  * Errors: SCI_EINVAL, SCI_ECAPACITY (workspace), SCI_EHIP.
  */
 size_t sci_stream_workspace_bytes(sci_ham_t ham, int64_t chunk);

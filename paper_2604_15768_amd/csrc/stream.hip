@@ -12,7 +12,7 @@
 namespace sci {
 
 struct StreamLayout {
-    size_t keys[2], hij[2], dedup, n_gen, total;
+    size_t keys[2], hij[2], dedup, n_gen, n_run, total;
 };
 
 static size_t al256s(size_t b) { return (b + 255) / 256 * 256; }
@@ -28,10 +28,33 @@ static StreamLayout stream_layout(int W, int64_t chunk) {
     }
     L.n_gen = off;
     off += 256;
+    L.n_run = off;
+    off += 256;
     L.dedup = off;
     off += sci_dedup_workspace_bytes(W, chunk);
     L.total = off;
     return L;
+}
+
+// events of one call, released on every return path (destroying an event with
+// work still pending on it is allowed; the release happens when it completes)
+struct StreamEvents {
+    hipEvent_t ready[2] = {nullptr, nullptr}, filled[2] = {nullptr, nullptr};
+    ~StreamEvents() {
+        for (int b = 0; b < 2; ++b) {
+            if (ready[b]) (void)hipEventDestroy(ready[b]);
+            if (filled[b]) (void)hipEventDestroy(filled[b]);
+        }
+    }
+};
+
+// After a merge that overflowed, *n_set_out holds the size the union needs, but
+// the set buffer holds only the first `cap` keys: the next chunk reads that many.
+__global__ void clamp_count_kernel(const int64_t *n, int64_t cap, int64_t *kept) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t v = *n;
+        *kept = v < cap ? v : cap;
+    }
 }
 
 }  // namespace sci
@@ -66,17 +89,12 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
     const int64_t n_chunks = exc_end > exc_begin ? ceil_div(exc_end - exc_begin, chunk) : 0;
 
     // ready[b]: buffer b consumed by the dedup stream; filled[b]: buffer b generated
-    hipEvent_t ready[2] = {nullptr, nullptr}, filled[2] = {nullptr, nullptr};
+    StreamEvents ev;
+    hipEvent_t *ready = ev.ready, *filled = ev.filled;
     for (int b = 0; b < 2; ++b) {
         SCI_HIP_TRY(hipEventCreateWithFlags(&ready[b], hipEventDisableTiming));
         SCI_HIP_TRY(hipEventCreateWithFlags(&filled[b], hipEventDisableTiming));
     }
-    auto cleanup = [&]() {
-        for (int b = 0; b < 2; ++b) {
-            if (ready[b]) (void)hipEventDestroy(ready[b]);
-            if (filled[b]) (void)hipEventDestroy(filled[b]);
-        }
-    };
 
     const uint64_t *cur_set = set_in;
     const int64_t *cur_n = set_in ? n_set_in : nullptr;
@@ -87,7 +105,6 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         st = sci_dedup_merge(W, nullptr, 0, cur_set, cur_n, set_a, n_set_out, set_capacity, nullptr, nullptr, 0,
                              ws + L.dedup, workspace_bytes - L.dedup, dev_flags, dedup_stream);
         *final_is_b = 0;
-        cleanup();
         return st;
     }
     // the dedup stream must not start before work already queued on the gen stream (inputs)
@@ -104,17 +121,19 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         SCI_HIP_TRY(hipEventRecord(filled[b], sg));
         SCI_HIP_TRY(hipStreamWaitEvent(sd, filled[b], 0));
         uint64_t *dst = out_b ? set_b : set_a;
-        // the set written two chunks ago is being read now; the running count lives in n_set_out
+        // the set written by the previous chunk is read now, with its kept count
         st = sci_dedup_merge(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
                              set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup, dev_flags,
                              dedup_stream);
         if (st != SCI_OK) break;
         SCI_HIP_TRY(hipEventRecord(ready[b], sd));
+        int64_t *n_run = (int64_t *)(ws + L.n_run);
+        SCI_LAUNCH(clamp_count_kernel, dim3(1), dim3(64), 0, sd, (const int64_t *)n_set_out, set_capacity, n_run);
+        SCI_HIP_TRY(hipGetLastError());
         cur_set = dst;
-        cur_n = n_set_out;
+        cur_n = n_run;
         out_b ^= 1;
     }
     *final_is_b = out_b ^ 1;
-    cleanup();
     return st;
 }

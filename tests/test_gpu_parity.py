@@ -369,6 +369,44 @@ def test_stream_dedup_matches_oracle(name, n_src, chunk):
     assert np.array_equal(sci.keys_to_host(out2[:int(n2.item())]), ou2)
 
 
+def test_stream_dedup_overflow_truncates_running_set():
+    """When the running set overflows its capacity mid-stream, later chunks merge into the
+    kept (first set_capacity) keys only.  Expected values follow that rule with the oracle:
+    R_0 = set_in, R_k = first cap keys of sorted(R_(k-1) | chunk_k), count = |R_(K-1) | chunk_K|."""
+    sci = require_gpu()
+    s = system("medium")
+    h = ham("medium")
+    dets = s.dets[pick_sources(s.dets.shape[0], 24, 7)]
+    ok, _, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
+    chunk = 150_000
+    bounds = [(e, min(e + chunk, ok.shape[0])) for e in range(0, ok.shape[0], chunk)]
+    assert len(bounds) == 5
+
+    def emulate(cap):
+        run, need = dets, dets.shape[0]
+        for e0, e1 in bounds:
+            u, _ = oracle.dedup_merge(s.W, ok[e0:e1], run)
+            need = u.shape[0]
+            run = u[:cap]
+        return run, need
+
+    sizes = []
+    run = dets
+    for e0, e1 in bounds[:2]:
+        run, _ = oracle.dedup_merge(s.W, ok[e0:e1], run)
+        sizes.append(run.shape[0])
+    cap = (sizes[0] + sizes[1]) // 2  # the second chunk overflows, three more follow
+    want, want_n = emulate(cap)
+    say(f"stream overflow: {ok.shape[0]} candidates, chunks of {chunk}, capacity {cap}")
+    d = sci.keys_to_device(dets)
+    out, n_out, flags = sci.stream_dedup(h, d, chunk, d, cap, dedup_stream=torch.cuda.Stream())
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "stream", allow=sci.FLAG_OVERFLOW) & sci.FLAG_OVERFLOW
+    n = int(n_out.item())
+    assert n == want_n and n >= cap
+    assert np.array_equal(sci.keys_to_host(out[:min(n, cap)]), want)
+
+
 # ---------------------------------------------------------------------------
 # differentiation: autograd wrapper, finite differences, dense-H gradient
 # ---------------------------------------------------------------------------
