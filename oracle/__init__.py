@@ -72,6 +72,10 @@ def _load():
         lib.ora_hpsi_rows.restype = i32
         lib.ora_dense_h.argtypes = [i32, i32, i32, i32, P, P, P, i64, P]
         lib.ora_dense_h.restype = i32
+        lib.ora_inverse_map.argtypes = [i32, P, i64, P, i64, P]
+        lib.ora_inverse_map.restype = i32
+        lib.ora_topk.argtypes = [i32, P, P, i64, i64, P]
+        lib.ora_topk.restype = i64
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = i32
         _lib = lib
@@ -212,6 +216,29 @@ def dedup_merge(W, cand, set_in=None):
     if got < 0:
         raise RuntimeError("oracle dedup capacity")
     return out[:got], novel[: nn.value]
+
+
+def inverse_map(W, u, cand):
+    """Position of each candidate in the strictly ascending set u (-1 if absent)."""
+    u = _dets(u, W) if np.asarray(u).size else np.zeros((0, W), dtype=np.uint64)
+    cand = _dets(cand, W) if np.asarray(cand).size else np.zeros((0, W), dtype=np.uint64)
+    idx = np.zeros(max(cand.shape[0], 1), dtype=np.int64)
+    rc = _load().ora_inverse_map(W, _p(u), u.shape[0], _p(cand), cand.shape[0], _p(idx))
+    if rc != 0:
+        raise ValueError("u is not strictly ascending")
+    return idx[: cand.shape[0]]
+
+
+def topk(W, keys, psi, K):
+    """Mask of the K entries of largest |psi| (equal magnitudes: smaller key first)."""
+    keys = _dets(keys, W) if np.asarray(keys).size else np.zeros((0, W), dtype=np.uint64)
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    assert psi.shape[0] == keys.shape[0]
+    mask = np.zeros(max(keys.shape[0], 1), dtype=np.uint8)
+    got = _load().ora_topk(W, _p(keys), _p(psi), keys.shape[0], int(K), _p(mask))
+    if got < 0:
+        raise ValueError("keys are not distinct")
+    return mask[: keys.shape[0]].astype(bool)
 
 
 def energy(n_orb, n_alpha, n_beta, h1, eri, sel, psi):

@@ -604,6 +604,63 @@ int ora_dense_h(int n_orb, int n_alpha, int n_beta, int W,
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* reverse index and selection                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Reverse index (paper section 2.2, energy evaluation; section 4.3 stage 3:
+ * each original configuration is searched in the unique set):
+ * idx[i] = position of cand[i] in the strictly ascending set u, or -1 when
+ * cand[i] is not in u.  Returns 0, or -1 if u is not strictly ascending.
+ */
+int ora_inverse_map(int W, const uint64_t *u, int64_t n_u, const uint64_t *cand, int64_t n, int64_t *idx)
+{
+    for (int64_t i = 1; i < n_u; ++i)
+        if (key_cmp(u + (i - 1) * W, u + i * W, W) >= 0) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) idx[i] = find_key(u, n_u, W, cand + i * W);
+    return 0;
+}
+
+/*
+ * Selection of the K most important candidates (paper section 2.2,
+ * wavefunction optimisation: top-K by inferred amplitude; section 4.3 stage 2):
+ * rank entries by |psi| descending, equal magnitudes by key ascending, and mark
+ * the first min(K, n) in mask.  With distinct keys the ranking is a total
+ * order, so the selection is unique.  NaN amplitudes are outside the contract.
+ * Returns the number marked, or -1 if two keys are equal.
+ */
+static int tk_W;
+static const uint64_t *tk_keys;
+static const double *tk_psi;
+static int tk_cmp(const void *a, const void *b)
+{
+    const int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    const double x = fabs(tk_psi[i]), y = fabs(tk_psi[j]);
+    if (x > y) return -1;
+    if (x < y) return 1;
+    return key_cmp(tk_keys + i * tk_W, tk_keys + j * tk_W, tk_W);
+}
+
+int64_t ora_topk(int W, const uint64_t *keys, const double *psi, int64_t n, int64_t K, uint8_t *mask)
+{
+    int64_t *order = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) order[i] = i;
+    tk_W = W;
+    tk_keys = keys;
+    tk_psi = psi;
+    qsort(order, (size_t)n, sizeof(int64_t), tk_cmp);
+    int dup = 0;
+    for (int64_t r = 1; r < n; ++r)
+        if (key_cmp(keys + order[r - 1] * W, keys + order[r] * W, W) == 0) dup = 1;
+    const int64_t k = K < n ? K : n;
+    memset(mask, 0, (size_t)n);
+    for (int64_t r = 0; r < k; ++r) mask[order[r]] = 1;
+    free(order);
+    return dup ? -1 : k;
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_select as select_pins
 
 MUTANTS = {
     # a dropped exchange term in the single-excitation element
@@ -42,6 +43,13 @@ MUTANTS = {
     "grad_factor": ("grad[i] = (double)(2.0L * (hp[i] - e * psi[i]) / den);", "grad[i] = (double)((hp[i] - e * psi[i]) / den);", 1),
     # diagonal left out of H psi
     "hpsi_no_diag": ("long double acc = (long double)diag_elem(&H, d) * psi[i];", "long double acc = 0.0L;", 2),
+    # reverse index reports the insertion point instead of -1 for absent keys
+    "inverse_absent_as_position": ("        else hi = mid;\n    }\n    return -1;\n}", "        else hi = mid;\n    }\n    return lo;\n}", 1),
+    # selection ranks by signed amplitude
+    "topk_signed": ("const double x = fabs(tk_psi[i]), y = fabs(tk_psi[j]);", "const double x = tk_psi[i], y = tk_psi[j];", 1),
+    # equal magnitudes broken by the larger key
+    "topk_tie_reversed": ("    return key_cmp(tk_keys + i * tk_W, tk_keys + j * tk_W, tk_W);\n}",
+                          "    return key_cmp(tk_keys + j * tk_W, tk_keys + i * tk_W, tk_W);\n}", 1),
 }
 
 PIN_CALLS = [
@@ -59,6 +67,10 @@ PIN_CALLS = [
     lambda: pins.test_energy_matches_dense_rayleigh_quotient(),
     lambda: pins.test_gradient_complex_step_and_finite_difference(),
     lambda: pins.test_eigenvector_has_zero_gradient(),
+    lambda: select_pins.test_inverse_map_matches_dictionary(1),
+    lambda: select_pins.test_inverse_map_special_cases(),
+    lambda: select_pins.test_topk_matches_sort(2),
+    lambda: select_pins.test_topk_special_cases(),
 ]
 
 
