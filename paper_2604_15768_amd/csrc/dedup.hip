@@ -49,11 +49,6 @@ struct DCfg {
 // small block-wide helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    const int lane = threadIdx.x & (kWave - 1);
-    return lane ? ((~0ull) >> (64 - lane)) : 0ull;
-}
-
 // exclusive scan of one int64 per thread across the block; returns the prefix, *total the sum
 __device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wave /*[kDWaves]*/) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -607,9 +602,12 @@ __global__ __launch_bounds__(kDThreads) void scan_apply_kernel(int64_t *x, const
 
 struct BucketArgs {
     const uint64_t *src;      // partitioned candidates (writable workspace unless single bucket)
-    uint64_t *dst;            // sorted unique run of each bucket, at the bucket's offset
+    uint64_t *dst;            // sorted unique run of each unit, at the unit's offset
     const int64_t *seg;       // [n_slots + 1] final bucket offsets
-    int64_t n_slots;
+    int64_t n_slots;          // bound on the number of units
+    const int32_t *ufirst;    // [n_units] first slot of each unit (consecutive buckets of one level-1 bucket)
+    const int32_t *uend;      // [n_units] one past its last slot
+    const int64_t *n_units;   // device count
     int two_level;            // 0: one bucket covering every key
     const int32_t *fan1;      // [1] level-1 fan-out
     const uint64_t *spl1;     // [F1-1][W]
@@ -618,14 +616,19 @@ struct BucketArgs {
     int F2;
     const uint64_t *B;        // running set (nullable)
     const int64_t *nB;        // nullable
-    int64_t *nuniq;           // [n_slots] unique candidates per bucket
-    int64_t *bstart;          // [n_slots] first set element in the bucket's key range
-    int64_t *bcount;          // [n_slots] set elements in the range
-    int64_t *ucount;          // [n_slots + 1] union size per bucket (scanned later)
-    int64_t *ncount;          // [n_slots + 1] novel size per bucket (scanned later)
-    int64_t *n_big;           // device count of oversized buckets
-    int64_t *big;             // [n_slots] their slot indices
+    int64_t *nuniq;           // [n_units] unique candidates per unit
+    int64_t *bstart;          // [n_units] first set element in the unit's key range
+    int64_t *bcount;          // [n_units] set elements in the range
+    int64_t *ucount;          // [n_units + 1] union size per unit (scanned later)
+    int64_t *ncount;          // [n_units + 1] novel size per unit (scanned later)
+    int64_t *n_big;           // device count of oversized units (single buckets above CAP)
+    int64_t *big;             // [n_units] their unit indices
 };
+
+__device__ __forceinline__ void unit_span(const BucketArgs &a, int64_t u, int64_t &start, int64_t &size) {
+    start = a.seg[a.ufirst[u]];
+    size = a.seg[a.uend[u]] - start;
+}
 
 // number of set elements <= k (upper bound) in B[0..n)
 template <int W>
@@ -679,22 +682,82 @@ __device__ bool slot_range(const BucketArgs &a, int64_t s, Key<W> &lo, bool &has
     return true;
 }
 
-// one thread per final slot: the set elements whose keys fall in the slot's range
+// one thread per unit: the set elements whose keys fall in the unit's range, the
+// lower bound of its first bucket to the upper bound of its last
 template <int W>
 __global__ void set_range_kernel(BucketArgs a) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.n_slots) return;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= *a.n_units) return;
     const int64_t nB = (a.B && a.nB) ? *a.nB : 0;
-    Key<W> lo, hi;
-    bool hl, hh;
+    Key<W> lo, hi, tmp;
+    bool hl, hh, t0;
     int64_t bl = 0, bh = 0;
-    if (nB > 0 && slot_range<W>(a, s, lo, hl, hi, hh)) {
+    if (nB > 0 && slot_range<W>(a, a.ufirst[u], lo, hl, tmp, t0) && slot_range<W>(a, a.uend[u] - 1, tmp, t0, hi, hh)) {
         bl = hl ? upper_bound_set<W>(a.B, nB, lo) : 0;
         bh = hh ? upper_bound_set<W>(a.B, nB, hi) : nB;
         if (bh < bl) bh = bl;
     }
-    a.bstart[s] = bl;
-    a.bcount[s] = bh - bl;
+    a.bstart[u] = bl;
+    a.bcount[u] = bh - bl;
+}
+
+// Units: consecutive final buckets of one level-1 bucket, greedily grouped while the
+// total stays within CAP keys (a bucket above CAP is a unit of its own).  Pass 0
+// counts each level-1 bucket's units, pass 1 (after a scan) writes them.
+template <int W, int PASS>
+__global__ void pack_units_kernel(BucketArgs a, int S1, int64_t *ucnt, int64_t *n_units1) {
+    using C = DCfg<W>;
+    const int s1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s1 > S1) return;
+    if (s1 == S1) {  // the scan's tail element, and the counts' zero tails
+        if (PASS == 0) ucnt[S1] = 0;
+        else {
+            const int64_t nu = ucnt[S1];
+            *n_units1 = nu + 1;
+            a.ucount[nu] = 0;
+            a.ncount[nu] = 0;
+        }
+        return;
+    }
+    const int f2 = s1 < a.fan1[0] ? a.fan2[s1] : 0;
+    const int32_t s0 = s1 * a.F2;
+    int64_t k = PASS == 0 ? 0 : ucnt[s1];
+    const int64_t k0 = k;
+    int32_t first = s0;
+    int64_t fill = 0;
+    for (int b = 0; b < f2; ++b) {
+        const int64_t sz = a.seg[s0 + b + 1] - a.seg[s0 + b];
+        if (b > first - s0 && fill + sz > C::CAP) {
+            if (PASS == 1) {
+                const_cast<int32_t *>(a.ufirst)[k] = first;
+                const_cast<int32_t *>(a.uend)[k] = s0 + b;
+            }
+            ++k;
+            first = s0 + b;
+            fill = 0;
+        }
+        fill += sz;
+    }
+    if (f2 > 0) {
+        if (PASS == 1) {
+            const_cast<int32_t *>(a.ufirst)[k] = first;
+            const_cast<int32_t *>(a.uend)[k] = s0 + f2;
+        }
+        ++k;
+    }
+    if (PASS == 0) ucnt[s1] = k - k0;
+}
+
+// one bucket covering every key: one unit
+__global__ void single_unit_kernel(BucketArgs a, int64_t *n_units1) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const_cast<int32_t *>(a.ufirst)[0] = 0;
+        const_cast<int32_t *>(a.uend)[0] = 1;
+        const_cast<int64_t *>(a.n_units)[0] = 1;
+        *n_units1 = 2;
+        a.ucount[1] = 0;
+        a.ncount[1] = 0;
+    }
 }
 
 struct BucketLds {
@@ -762,8 +825,10 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     __shared__ int s_u[kDWaves];
     __shared__ int64_t s_wsum[kDWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int64_t s = blockIdx.x;
-    const int64_t start = a.seg[s], size = a.seg[s + 1] - a.seg[s];
+    const int64_t s = blockIdx.x;  // unit
+    if (s >= *a.n_units) return;
+    int64_t start, size;
+    unit_span(a, s, start, size);
     const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
 
     int64_t nu = 0, matches = 0;
@@ -960,7 +1025,8 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
     const int64_t n_big = *a.n_big;
     for (int64_t t = blockIdx.x; t < n_big; t += gridDim.x) {
         const int64_t s = a.big[t];
-        const int64_t start = a.seg[s], size = a.seg[s + 1] - a.seg[s];
+        int64_t start, size;
+        unit_span(a, s, start, size);
         const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
         uint64_t *X = const_cast<uint64_t *>(a.src) + start * W;
         uint64_t *Y = a.dst + start * W;
@@ -1000,11 +1066,14 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
 // emit: per bucket, merge its unique run with the set elements of its range
 // into set_out at the scanned union offset; novel keys at the novel offset
 // ---------------------------------------------------------------------------
-constexpr int kMergePer = 8;  // merged positions per thread per round
+constexpr int kMergePer = 4;                     // merged positions per thread per window
+constexpr int kEmitStep = kDThreads * kMergePer;  // outputs per staged merge window
 
 struct EmitArgs {
-    const uint64_t *runs;     // bucket unique runs (at seg offsets)
+    const uint64_t *runs;     // unit unique runs (at their first bucket's seg offset)
     const int64_t *seg;
+    const int32_t *ufirst;
+    const int64_t *n_units;
     const int64_t *nuniq, *bstart, *bcount;
     const int64_t *uoff, *noff;  // scanned ucount / ncount
     const uint64_t *B;
@@ -1014,15 +1083,23 @@ struct EmitArgs {
     int64_t novel_cap;
 };
 
+// Run keys among the first k outputs of merge(A, B) (ties: B first), searched by one
+// wave: each round probes 64 evenly spaced split points and keeps the interval
+// between the last that is still too low and the first that is not.
 template <int W>
-__device__ __forceinline__ int64_t merge_path(const uint64_t *A, int64_t nA, const uint64_t *B, int64_t nB,
-                                              int64_t k) {
-    // elements of A among the first k of the merge (ties: B first)
-    int64_t lo = k > nB ? k - nB : 0, hi = k < nA ? k : nA;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (key_less<W>(load_key<W>(A, mid), load_key<W>(B, k - mid - 1))) lo = mid + 1;
-        else hi = mid;
+__device__ int64_t wave_merge_path(const uint64_t *A, int64_t nA, const uint64_t *B, int64_t nB, int64_t k) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t lo = k > nB ? k - nB : 0, hi = k < nA ? k : nA;  // answer in [lo, hi]
+    while (hi > lo) {
+        const int64_t span = hi - lo;
+        const int64_t x = lo + (span * lane) / kWave;  // probes cover [lo, hi) once span <= 64
+        const bool p = key_less<W>(load_key<W>(A, x), load_key<W>(B, k - x - 1));
+        const int t = __popcll(__ballot(p));  // the true probes form a prefix of the lanes
+        if (t == 0) return lo;
+        const int64_t last_true = lo + (span * (t - 1)) / kWave;
+        const int64_t first_false = t < kWave ? lo + (span * t) / kWave : hi;
+        lo = last_true + 1;
+        hi = first_false;
     }
     return lo;
 }
@@ -1030,8 +1107,9 @@ __device__ __forceinline__ int64_t merge_path(const uint64_t *A, int64_t nA, con
 template <int W>
 __global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
-    const int64_t s = blockIdx.x;
-    const uint64_t *A = a.runs + a.seg[s] * W;
+    const int64_t s = blockIdx.x;  // unit
+    if (s >= *a.n_units) return;
+    const uint64_t *A = a.runs + a.seg[a.ufirst[s]] * W;
     const int64_t nA = a.nuniq[s];
     const uint64_t *Bs = a.B ? a.B + a.bstart[s] * W : nullptr;
     const int64_t nBs = a.bcount[s];
@@ -1059,32 +1137,54 @@ __global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
         }
         return;
     }
-    const int64_t step = (int64_t)kDThreads * kMergePer;
-    for (int64_t c0 = 0; c0 < total; c0 += step) {
-        const int64_t p0 = c0 + (int64_t)threadIdx.x * kMergePer;
-        const int64_t p1 = p0 + kMergePer < total ? p0 + kMergePer : total;
+    // general case: merge the run with the set keys in this slot's range, one window of
+    // kEmitStep outputs per round with both inputs staged in LDS.  Only window ends
+    // inside the merge need a split search over global memory.
+    __shared__ Key<W> sA[kEmitStep];
+    __shared__ Key<W> sB[kEmitStep + 1];  // sB[0]: the set key just before the window
+    __shared__ int64_t s_cut;
+    int64_t i0 = 0;  // run keys consumed by earlier windows
+    for (int64_t c0 = 0; c0 < total; c0 += kEmitStep) {
+        const int64_t c1 = c0 + kEmitStep < total ? c0 + kEmitStep : total;
+        if (threadIdx.x < kWave) {
+            const int64_t cut = (c1 == total) ? nA : wave_merge_path<W>(A, nA, Bs, nBs, c1);
+            if (threadIdx.x == 0) s_cut = cut;
+        }
+        __syncthreads();
+        const int64_t i1 = s_cut;
+        const int64_t j0 = c0 - i0;
+        const int na = (int)(i1 - i0), nb = (int)((c1 - i1) - j0);
+        for (int t = threadIdx.x; t < na; t += kDThreads) sA[t] = load_key<W>(A, i0 + t);
+        for (int t = threadIdx.x; t <= nb; t += kDThreads)
+            if (t > 0 || j0 > 0) sB[t] = load_key<W>(Bs, j0 - 1 + t);
+        __syncthreads();
+        const int p0 = threadIdx.x * kMergePer;
+        const int win = (int)(c1 - c0);
+        const int cnt = p0 < win ? (win - p0 < kMergePer ? win - p0 : kMergePer) : 0;
         Key<W> vals[kMergePer];
         uint32_t fa = 0, fd = 0;
-        int cnt = 0;
-        if (p0 < p1) {
-            int64_t i = merge_path<W>(A, nA, Bs, nBs, p0);
-            int64_t j = p0 - i;
-            cnt = (int)(p1 - p0);
+        if (cnt > 0) {
+            // run keys among this window's first p0 outputs (ties: set key first)
+            int lo = p0 > nb ? p0 - nb : 0, hi = p0 < na ? p0 : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_less<W>(sA[mid], sB[p0 - mid])) lo = mid + 1;
+                else hi = mid;
+            }
+            int i = lo, j = p0 - lo;
 #pragma unroll
             for (int q = 0; q < kMergePer; ++q) {
                 if (q < cnt) {
-                    bool takeA;
-                    if (i >= nA) takeA = false;
-                    else if (j >= nBs) takeA = true;
-                    else takeA = key_less<W>(load_key<W>(A, i), load_key<W>(Bs, j));
+                    const bool takeA = i < na && (j >= nb || key_less<W>(sA[i], sB[1 + j]));
                     if (takeA) {
-                        const Key<W> x = load_key<W>(A, i);
+                        const Key<W> x = sA[i];
                         vals[q] = x;
                         fa |= 1u << q;
-                        if (j > 0 && key_eq<W>(load_key<W>(Bs, j - 1), x)) fd |= 1u << q;
+                        // equal to the set key emitted just before it: already in the union
+                        if (j0 + j > 0 && key_eq<W>(sB[j], x)) fd |= 1u << q;
                         ++i;
                     } else {
-                        vals[q] = load_key<W>(Bs, j);
+                        vals[q] = sB[1 + j];
                         ++j;
                     }
                 }
@@ -1114,6 +1214,8 @@ __global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
         }
         ou += tu;
         on += tn;
+        i0 = i1;
+        __syncthreads();  // the next window overwrites sA / sB
     }
 }
 
@@ -1154,7 +1256,7 @@ __global__ void check_sorted_kernel(const uint64_t *S, const int64_t *nS, uint32
 // ---------------------------------------------------------------------------
 struct WsLayout {
     size_t bufA, bufB, ids, segA, segB, fan1, fan2, spl1, spl2, tile_base, cbase, counts, sums, samples;
-    size_t nuniq, bstart, bcount, ucount, ncount, big, scal;
+    size_t nuniq, bstart, bcount, ucount, ncount, big, ufirst, uend, ucnt, scal;
     size_t total;
     int64_t max_counts, max_sums, n_final_slots;
 };
@@ -1198,13 +1300,18 @@ static WsLayout ws_layout(int64_t n) {
     L.ucount = take((size_t)(S2 + 1) * 8);
     L.ncount = take((size_t)(S2 + 1) * 8);
     L.big = take((size_t)S2 * 8);
+    L.ufirst = take((size_t)(S2 + 1) * 4);
+    L.uend = take((size_t)(S2 + 1) * 4);
+    L.ucnt = take((size_t)(S1 + 2) * 8);
     L.scal = take(64);
     L.total = off;
     return L;
 }
 
-static hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_t *sums, int64_t *total_out,
-                              hipStream_t st) {
+int64_t device_scan_sums(int64_t n_bound) { return ceil_div(std::max<int64_t>(n_bound, 1), kScanPer) + 1; }
+
+hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_t *sums, int64_t *total_out,
+                       hipStream_t st) {
     const int64_t nb = std::max<int64_t>(1, ceil_div(n_bound, kScanPer));
     SCI_LAUNCH(scan_reduce_kernel, dim3((unsigned)nb), dim3(kDThreads), 0, st, (const int64_t *)x, n_dev, n_bound, sums);
     SCI_LAUNCH(scan_sums_kernel, dim3(1), dim3(kDThreads), 0, st, sums, nb, total_out);
@@ -1222,7 +1329,8 @@ __global__ void init_level0_kernel(int64_t *seg, int64_t n) {
 template <int W>
 static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_in, const int64_t *n_set_in,
                           uint64_t *set_out, int64_t *n_set_out, int64_t set_cap, uint64_t *novel,
-                          int64_t *n_novel, int64_t novel_cap, char *ws, uint32_t *flags, hipStream_t st) {
+                          int64_t *n_novel, int64_t novel_cap, char *ws, uint32_t *flags, hipStream_t st,
+                          bool check_set) {
     using C = DCfg<W>;
     const WsLayout L = ws_layout<W>(n);
     uint64_t *bufA = (uint64_t *)(ws + L.bufA);
@@ -1231,10 +1339,11 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     int64_t *segB = (int64_t *)(ws + L.segB);
     int64_t *counts = (int64_t *)(ws + L.counts);
     int64_t *sums = (int64_t *)(ws + L.sums);
-    int64_t *scal = (int64_t *)(ws + L.scal);  // [0] union total, [1] novel total, [2] level counters
+    // [0] union total, [1] novel total, [2] level counters, [3] oversized units, [4] units, [5] units + 1
+    int64_t *scal = (int64_t *)(ws + L.scal);
     const bool have_set = set_in && n_set_in;
 
-    if (have_set)
+    if (have_set && check_set)
         SCI_LAUNCH(check_sorted_kernel<W>, dim3(1024), dim3(256), 0, st, set_in, n_set_in, flags);
     if (n == 0) {
         SCI_LAUNCH(copy_keys_kernel<W>, dim3(4096), dim3(256), 0, st, set_in, have_set ? n_set_in : nullptr, set_out,
@@ -1251,12 +1360,21 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     }
 
     BucketArgs b{};
+    b.ufirst = (const int32_t *)(ws + L.ufirst);
+    b.uend = (const int32_t *)(ws + L.uend);
+    b.n_units = scal + 4;
+    b.ucount = (int64_t *)(ws + L.ucount);
+    b.ncount = (int64_t *)(ws + L.ncount);
+    b.fan1 = (const int32_t *)(ws + L.fan1);
+    b.fan2 = (const int32_t *)(ws + L.fan2);
+    b.F2 = C::F2;
     SCI_LAUNCH(init_level0_kernel, dim3(1), dim3(64), 0, st, segA, n);
     if (n <= C::CAP) {
         b.src = cand;  // one bucket: read only
         b.seg = segA;
         b.n_slots = 1;
         b.two_level = 0;
+        SCI_LAUNCH(single_unit_kernel, dim3(1), dim3(64), 0, st, b, scal + 5);
     } else {
         const uint64_t *cur = cand;
         const int64_t *seg_cur = segA;
@@ -1322,20 +1440,21 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
         b.seg = segA;  // level-2 output segments
         b.n_slots = S_cur;
         b.two_level = 1;
+        // group consecutive buckets into units of at most CAP keys
+        int64_t *ucnt = (int64_t *)(ws + L.ucnt);
+        const unsigned pg = (unsigned)ceil_div(C::F1 + 1, 256);
+        SCI_LAUNCH((pack_units_kernel<W, 0>), dim3(pg), dim3(256), 0, st, b, (int)C::F1, ucnt, scal + 5);
+        SCI_HIP_TRY(device_scan(ucnt, nullptr, C::F1 + 1, sums, scal + 4, st));
+        SCI_LAUNCH((pack_units_kernel<W, 1>), dim3(pg), dim3(256), 0, st, b, (int)C::F1, ucnt, scal + 5);
     }
     b.dst = bufA;
-    b.fan1 = (const int32_t *)(ws + L.fan1);
     b.spl1 = (const uint64_t *)(ws + L.spl1);
-    b.fan2 = (const int32_t *)(ws + L.fan2);
     b.spl2 = (const uint64_t *)(ws + L.spl2);
-    b.F2 = C::F2;
     b.B = have_set ? set_in : nullptr;
     b.nB = have_set ? n_set_in : nullptr;
     b.nuniq = (int64_t *)(ws + L.nuniq);
     b.bstart = (int64_t *)(ws + L.bstart);
     b.bcount = (int64_t *)(ws + L.bcount);
-    b.ucount = (int64_t *)(ws + L.ucount);
-    b.ncount = (int64_t *)(ws + L.ncount);
     SCI_LAUNCH(set_range_kernel<W>, dim3((unsigned)ceil_div(b.n_slots, 256)), dim3(256), 0, st, b);
     b.n_big = scal + 3;
     b.big = (int64_t *)(ws + L.big);
@@ -1343,13 +1462,13 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     SCI_LAUNCH(bucket_kernel<W>, dim3((unsigned)b.n_slots), dim3(kDThreads), 0, st, b);
     SCI_LAUNCH(bucket_big_kernel<W>, dim3(4096), dim3(kDThreads), 0, st, b);
     SCI_HIP_TRY(hipGetLastError());
-    SCI_HIP_TRY(launch_set_i64(b.ucount + b.n_slots, 0, st));
-    SCI_HIP_TRY(launch_set_i64(b.ncount + b.n_slots, 0, st));
-    SCI_HIP_TRY(device_scan(b.ucount, nullptr, b.n_slots + 1, sums, scal + 0, st));
-    SCI_HIP_TRY(device_scan(b.ncount, nullptr, b.n_slots + 1, sums, scal + 1, st));
+    SCI_HIP_TRY(device_scan(b.ucount, scal + 5, b.n_slots + 1, sums, scal + 0, st));
+    SCI_HIP_TRY(device_scan(b.ncount, scal + 5, b.n_slots + 1, sums, scal + 1, st));
     EmitArgs e{};
     e.runs = bufA;
     e.seg = b.seg;
+    e.ufirst = b.ufirst;
+    e.n_units = b.n_units;
     e.nuniq = b.nuniq;
     e.bstart = b.bstart;
     e.bcount = b.bcount;
@@ -1378,11 +1497,14 @@ extern "C" size_t sci_dedup_workspace_bytes(int32_t n_words, int64_t n_cand) {
     return 0;
 }
 
-extern "C" int32_t sci_dedup_merge(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
-                                   const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out,
-                                   int64_t set_capacity, uint64_t *novel, int64_t *n_novel, int64_t novel_capacity,
-                                   void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
-                                   sci_stream_t stream) {
+namespace sci {
+
+// sci_dedup_merge with the strict-order check of set_in optional: callers that pass a
+// set this library produced skip the extra pass over it.
+int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
+                            const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
+                            uint64_t *novel, int64_t *n_novel, int64_t novel_capacity, void *workspace,
+                            size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in) {
     set_error("");
     if (n_words < 1 || n_words > SCI_MAX_WORDS)
         return fail(n_words < 1 ? SCI_EINVAL : SCI_EUNSUPPORTED, "sci_dedup_merge: n_words=%d", n_words);
@@ -1399,10 +1521,21 @@ extern "C" int32_t sci_dedup_merge(int32_t n_words, const uint64_t *cand, int64_
     const size_t need = sci_dedup_workspace_bytes(n_words, n_cand);
     if (workspace_bytes < need)
         return fail(SCI_ECAPACITY, "sci_dedup_merge: workspace %zu < %zu bytes", workspace_bytes, need);
-    hipStream_t st = (hipStream_t)stream;
     if (n_words == 1)
         return dedup_impl<1>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                             novel_capacity, (char *)workspace, dev_flags, st);
+                             novel_capacity, (char *)workspace, dev_flags, st, check_set_in);
     return dedup_impl<2>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                         novel_capacity, (char *)workspace, dev_flags, st);
+                         novel_capacity, (char *)workspace, dev_flags, st, check_set_in);
+}
+
+}  // namespace sci
+
+extern "C" int32_t sci_dedup_merge(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
+                                   const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out,
+                                   int64_t set_capacity, uint64_t *novel, int64_t *n_novel, int64_t novel_capacity,
+                                   void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
+                                   sci_stream_t stream) {
+    return sci::dedup_merge_checked(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel,
+                                    n_novel, novel_capacity, workspace, workspace_bytes, dev_flags,
+                                    (hipStream_t)stream, true);
 }

@@ -198,6 +198,24 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv &f, uint32_t 
 inline int64_t comb2(int64_t x) { return x * (x - 1) / 2; }
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// lanes below this one in the wavefront
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & (kWave - 1);
+    return lane ? ((~0ull) >> (64 - lane)) : 0ull;
+}
+
+// Device-wide exclusive scan of int64 x[0..n), n = *n_dev when n_dev is given, else
+// n_bound; sums holds device_scan_sums(n_bound) entries; *total_out (nullable) gets the sum.
+hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_t *sums, int64_t *total_out,
+                       hipStream_t st);
+int64_t device_scan_sums(int64_t n_bound);
+
+// sci_dedup_merge, with the strict-order check of set_in optional
+int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
+                            const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
+                            uint64_t *novel, int64_t *n_novel, int64_t novel_capacity, void *workspace,
+                            size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in);
 __host__ __device__ inline int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace sci

@@ -121,10 +121,11 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         SCI_HIP_TRY(hipEventRecord(filled[b], sg));
         SCI_HIP_TRY(hipStreamWaitEvent(sd, filled[b], 0));
         uint64_t *dst = out_b ? set_b : set_a;
-        // the set written by the previous chunk is read now, with its kept count
-        st = sci_dedup_merge(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
-                             set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup, dev_flags,
-                             dedup_stream);
+        // the set written by the previous chunk is read now, with its kept count; only the
+        // caller's set_in needs the order check
+        st = dedup_merge_checked(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
+                                 set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup,
+                                 dev_flags, sd, /*check_set_in=*/k == 0);
         if (st != SCI_OK) break;
         SCI_HIP_TRY(hipEventRecord(ready[b], sd));
         int64_t *n_run = (int64_t *)(ws + L.n_run);
