@@ -39,7 +39,140 @@ def parse():
     ap.add_argument("--cpu-sources", type=int, default=8000)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the large-workload streaming and energy/autograd timings")
+    ap.add_argument("--large-sources", type=int, default=4096)
+    ap.add_argument("--large-chunk", type=int, default=1 << 28)
     return ap.parse_args()
+
+
+def _median_ms(fn, reps, torch):
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def select_extras(torch, sci, keys, n_cand, union, n_union_dev, n_union, sel, n_sel, W, ws_d):
+    """Reverse index of every generated candidate into the union, and top-K of
+    synthetic amplitudes over the novel candidates (union minus S)."""
+    dev = keys.device
+    out = {}
+    index = torch.empty(sci.sci_index_bytes(W, n_union), dtype=torch.uint8, device=dev)
+    idx = torch.empty(n_cand, dtype=torch.int64, device=dev)
+    flags = sci.new_flags(dev)
+    build = lambda: sci.sci_index_build(W, union, n_union_dev, n_union, index, index.numel(), flags)
+    look = lambda: sci.sci_index_lookup(W, index, index.numel(), keys, n_cand, idx)
+    build()
+    look()
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "reverse index")
+    assert int((idx[:: max(1, n_cand // 100000)] < 0).sum().item()) == 0, "reverse index: candidate not found"
+    b_ms = _median_ms(build, 3, torch)
+    l_ms = _median_ms(look, 3, torch)
+    out["index"] = {"n_set": n_union, "table_bytes": index.numel(), "build_ms": b_ms, "n_lookups": n_cand,
+                    "lookup_ms": l_ms, "lookups_per_s": n_cand / (l_ms / 1000.0),
+                    "lookup_stream_GBps": n_cand * (8 * W + 8) / (l_ms / 1000.0) / 1e9}
+    del index, idx
+    torch.cuda.empty_cache()
+    # the novel set, and amplitudes for it drawn on the device (synthetic stand-in for inference)
+    n_set_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    novel = torch.empty((n_union, W), dtype=torch.int64, device=dev)
+    n_novel = torch.zeros(1, dtype=torch.int64, device=dev)
+    tmp = torch.empty((n_union + n_sel, W), dtype=torch.int64, device=dev)
+    n_tmp = torch.zeros(1, dtype=torch.int64, device=dev)
+    sci.sci_dedup_merge(W, keys, n_cand, sel, n_set_in, tmp, n_tmp, tmp.shape[0], novel, n_novel, n_union,
+                        ws_d, ws_d.numel(), flags)
+    torch.cuda.synchronize()
+    del tmp
+    nn = int(n_novel.item())
+    g = torch.Generator(device=dev)
+    g.manual_seed(2604157680)
+    psi = torch.randn(nn, dtype=torch.float64, device=dev, generator=g)
+    K = 100_000
+    ok = torch.empty((K, W), dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(sci.sci_topk_workspace_bytes(nn), dtype=torch.uint8, device=dev)
+    run = lambda: sci.sci_topk(W, novel, psi, nn, K, ok, None, n_out, K, ws, ws.numel(), flags)
+    run()
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "topk")
+    t_ms = _median_ms(run, 3, torch)
+    out["topk"] = {"n": nn, "k": K, "ms": t_ms, "entries_per_s": nn / (t_ms / 1000.0), "n_selected": int(n_out.item())}
+    return out
+
+
+def large_extras(args, torch, sci, si):
+    """Large workload (n_orb=60, 10a+10b, W=2): the first `large_sources` sources of S
+    streamed through the device pool (generation of chunk k+1 overlapping dedup-merge
+    of chunk k into S), and E / E+dE/dpsi over all of S, plain and through autograd."""
+    wl = si.WORKLOADS["large"]
+    sysm = si.make_system(wl)
+    dev = torch.device("cuda", 0)
+    ham = sci.Ham(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri)
+    sel = sci.keys_to_device(sysm.dets)
+    n_sel = sel.shape[0]
+    n_src = min(args.large_sources, n_sel)
+    dets = sel[:n_src]
+    total = n_src * ham.n_coupled
+    chunk = args.large_chunk
+    cap = total + n_sel
+    W = ham.W
+    set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
+    set_b = torch.empty_like(set_a)
+    n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(sci.sci_stream_workspace_bytes(ham, chunk), dtype=torch.uint8, device=dev)
+    flags = sci.new_flags(dev)
+    gen_stream = torch.cuda.current_stream()
+    dd_stream = torch.cuda.Stream()
+
+    def run():
+        sci.sci_stream_dedup(ham, dets, n_src, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out,
+                             ws, ws.numel(), flags, gen_stream, dd_stream)
+        torch.cuda.current_stream().wait_stream(dd_stream)
+
+    run()
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "large stream warmup")
+    sci.sci_profile_read()
+    sci.sci_profile_enable(True)
+    t_ms = _median_ms(run, 3, torch)
+    torch.cuda.synchronize()
+    kern = {}
+    for name, ms in sci.sci_profile_read():
+        kern[name] = kern.get(name, 0.0) + ms / 3
+    sci.sci_profile_enable(False)
+    sci.check_flags(flags, "large stream")
+    n_union = int(n_out.item())
+    del set_a, set_b, ws
+    out = {
+        "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
+                    f"first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
+        "n_candidates": total, "n_unique_union": n_union, "ms": t_ms,
+        "candidates_per_s": total / (t_ms / 1000.0),
+        "kernel_ms": {k: round(v, 3) for k, v in sorted(kern.items(), key=lambda x: -x[1]) if v >= 0.05},
+    }
+    # energy and gradient over the large S: plain entry point and the autograd path
+    psi = torch.from_numpy(sysm.psi).to(dev)
+    e_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=False), 5, torch)
+    eg_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=True), 5, torch)
+
+    def auto():
+        p = psi.clone().requires_grad_(True)
+        e = sci.SciEnergy.apply(p, ham, sel)
+        e.backward()
+
+    ag_ms = _median_ms(auto, 5, torch)
+    energy = {"workload": f"{wl.name}: E over all {n_sel} selected determinants", "n_sel": n_sel,
+              "energy_ms": e_ms, "energy_grad_ms": eg_ms, "autograd_fwd_bwd_ms": ag_ms}
+    return out, energy
 
 
 def recorded_traffic(kernel_name, W):
@@ -231,6 +364,13 @@ def main():
         "gen_roofline": {"bound": "hbm", "achieved": gen_bytes / (g_ms / 1000.0) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gen_bytes / (g_ms / 1000.0) / 1e9 / HBM_PEAK_GBS},
     }
+    if not args.no_extras:
+        result["extras"] = {"reverse_index_topk": select_extras(torch, sci, keys, n_cand, set_out, n_set_out,
+                                                                 n_unique, sel, n_sel, W, ws_d)}
+        del keys, hij, set_out, ws_d
+        torch.cuda.empty_cache()
+        ls, eg = large_extras(args, torch, sci, si)
+        result["extras"].update({"large_stream": ls, "energy_grad_large": eg})
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, args.cpu_sources)
     print(json.dumps(result), flush=True)

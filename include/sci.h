@@ -215,6 +215,56 @@ int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
                          sci_stream_t gen_stream, sci_stream_t dedup_stream);
 
 /*
+ * Reverse index (paper section 2.2: every coupled configuration mapped to its
+ * entry in the unique set; section 4.3 stage 3: each original configuration
+ * searched in the unique set).
+ *
+ * sci_index_bytes: size of an index over at most set_bound keys (a header and
+ * an open-addressing table of 2^ceil(log2(2*set_bound)) slots of 16 bytes for
+ * W=1, 32 bytes for W=2; at least 64 slots).
+ *
+ * sci_index_build: load the strictly ascending set (device [*n_set][W], count
+ * on the device) into `index` (device, caller-owned, at least
+ * sci_index_bytes(n_words, set_bound) bytes).  If *n_set > set_bound,
+ * SCI_FLAG_OVERFLOW is set and only the first set_bound keys are indexed.
+ * The set must stay unchanged while the index is used.
+ *
+ * sci_index_lookup: idx[i] (device int64) = position of cand[i] in the set,
+ * or -1 when the key is not in it, for i < n_cand; cand is device
+ * [n_cand][W], any order.  Deterministic (positions, not probe order).  An
+ * index buffer that sci_index_build did not fill for this n_words gives -1
+ * for every candidate (the kernel checks the header against index_bytes).
+ * Errors: SCI_EINVAL, SCI_EUNSUPPORTED (n_words), SCI_ECAPACITY (index too
+ * small), SCI_EHIP.
+ */
+size_t sci_index_bytes(int32_t n_words, int64_t set_bound);
+int32_t sci_index_build(int32_t n_words, const uint64_t *set, const int64_t *n_set, int64_t set_bound,
+                        void *index, size_t index_bytes, uint32_t *dev_flags, sci_stream_t stream);
+int32_t sci_index_lookup(int32_t n_words, const void *index, size_t index_bytes,
+                         const uint64_t *cand, int64_t n_cand, int64_t *idx, sci_stream_t stream);
+
+/*
+ * Top-K selection (paper section 2.2: the candidates with the largest
+ * inferred amplitudes are added to S; section 4.3 stage 2).
+ *
+ * Ranks the n entries (keys device [n][W], distinct; psi device [n] FP64) by
+ * |psi| descending, equal magnitudes by key ascending, and writes the first
+ * min(k, n) of that ranking, in input order, to out_keys ([capacity][W]) and
+ * out_psi (nullable, [capacity]); *n_out (device int64) gets their number.
+ * The selection is unique and bit-exact for distinct keys; with repeated keys
+ * more entries may tie (SCI_FLAG_OVERFLOW if they exceed capacity).  NaN
+ * amplitudes are outside the contract.  Merging the result into S is a call
+ * of sci_dedup_merge.
+ * workspace: device, at least sci_topk_workspace_bytes(n) bytes.
+ * Errors: SCI_EINVAL, SCI_EUNSUPPORTED (n_words), SCI_ECAPACITY (capacity <
+ * min(k, n), or workspace), SCI_EHIP.
+ */
+size_t sci_topk_workspace_bytes(int64_t n);
+int32_t sci_topk(int32_t n_words, const uint64_t *keys, const double *psi, int64_t n, int64_t k,
+                 uint64_t *out_keys, double *out_psi, int64_t *n_out, int64_t capacity,
+                 void *workspace, size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream);
+
+/*
  * Per-kernel timing, for profiling and roofline reports (not part of the
  * method).  While enabled (process-wide), every kernel the library launches
  * is bracketed by two HIP events recorded on that kernel's stream.

@@ -63,6 +63,16 @@ _lib.sci_stream_workspace_bytes.restype = _sz
 _lib.sci_stream_dedup.argtypes = [_P, _P, _i64, _i64, _i64, _i64, _P, _P, _P, _P, _i64, _P,
                                   ctypes.POINTER(_i32), _P, _sz, _P, _P, _P]
 _lib.sci_stream_dedup.restype = _i32
+_lib.sci_index_bytes.argtypes = [_i32, _i64]
+_lib.sci_index_bytes.restype = _sz
+_lib.sci_index_build.argtypes = [_i32, _P, _P, _i64, _P, _sz, _P, _P]
+_lib.sci_index_build.restype = _i32
+_lib.sci_index_lookup.argtypes = [_i32, _P, _sz, _P, _i64, _P, _P]
+_lib.sci_index_lookup.restype = _i32
+_lib.sci_topk_workspace_bytes.argtypes = [_i64]
+_lib.sci_topk_workspace_bytes.restype = _sz
+_lib.sci_topk.argtypes = [_i32, _P, _P, _i64, _i64, _P, _P, _P, _i64, _P, _sz, _P, _P]
+_lib.sci_topk.restype = _i32
 _lib.sci_profile_enable.argtypes = [_i32]
 _lib.sci_profile_enable.restype = _i32
 _lib.sci_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), _i32]
@@ -307,6 +317,64 @@ def stream_dedup(ham: Ham, dets: torch.Tensor, chunk: int, set_in: torch.Tensor,
     is_b = sci_stream_dedup(ham, dets, n, exc_begin, exc_end, chunk, set_in, n_in, set_a, set_b, set_capacity, n_out,
                             ws, ws.numel(), flags, gen_stream, dedup_stream)
     return (set_b if is_b else set_a), n_out, flags
+
+
+def sci_index_bytes(n_words: int, set_bound: int) -> int:
+    return int(_lib.sci_index_bytes(n_words, set_bound))
+
+
+def sci_index_build(n_words, set_keys, n_set, set_bound, index, index_bytes, dev_flags, stream=None):
+    _check(_lib.sci_index_build(n_words, _ptr(set_keys), _ptr(n_set), set_bound, _ptr(index), index_bytes,
+                                _ptr(dev_flags), _stream(stream)), "sci_index_build")
+
+
+def sci_index_lookup(n_words, index, index_bytes, cand, n_cand, idx, stream=None):
+    _check(_lib.sci_index_lookup(n_words, _ptr(index), index_bytes, _ptr(cand), n_cand, _ptr(idx), _stream(stream)),
+           "sci_index_lookup")
+
+
+def sci_topk_workspace_bytes(n: int) -> int:
+    return int(_lib.sci_topk_workspace_bytes(n))
+
+
+def sci_topk(n_words, keys, psi, n, k, out_keys, out_psi, n_out, capacity, workspace, workspace_bytes, dev_flags,
+             stream=None):
+    _check(_lib.sci_topk(n_words, _ptr(keys), _ptr(psi), n, k, _ptr(out_keys), _ptr(out_psi), _ptr(n_out), capacity,
+                         _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_topk")
+
+
+def build_index(set_keys: torch.Tensor, n_set: torch.Tensor, set_bound: int, W: int, flags=None):
+    """Reverse-index table over the strictly ascending set (count n_set on the device)."""
+    dev = set_keys.device
+    nbytes = sci_index_bytes(W, set_bound)
+    index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    sci_index_build(W, set_keys, n_set, set_bound, index, nbytes, flags)
+    return index, flags
+
+
+def inverse_map(index: torch.Tensor, cand: torch.Tensor, W: int):
+    """Position of each candidate in the indexed set, -1 when absent."""
+    n = cand.shape[0]
+    idx = torch.empty(max(n, 1), dtype=torch.int64, device=cand.device)
+    sci_index_lookup(W, index, index.numel(), cand, n, idx)
+    return idx[:n]
+
+
+def topk(keys: torch.Tensor, psi: torch.Tensor, k: int, W: int, flags=None):
+    """The min(k, n) entries of largest |psi| (ties: smaller key), in input order."""
+    dev = keys.device
+    n = keys.shape[0]
+    kk = min(k, n)
+    out_keys = torch.empty((max(kk, 1), W), dtype=torch.int64, device=dev)
+    out_psi = torch.empty(max(kk, 1), dtype=torch.float64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(sci_topk_workspace_bytes(n), 1), dtype=torch.uint8, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    sci_topk(W, keys, psi, n, k, out_keys, out_psi, n_out, kk, ws, ws.numel(), flags)
+    return out_keys, out_psi, n_out, flags
 
 
 class SciEnergy(torch.autograd.Function):

@@ -50,7 +50,8 @@ struct DCfg {
 // ---------------------------------------------------------------------------
 
 // exclusive scan of one int64 per thread across the block; returns the prefix, *total the sum
-__device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wave /*[kDWaves]*/) {
+template <int NW = kDWaves>
+__device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wave /*[NW]*/) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     int64_t x = v;
     for (int o = 1; o < kWave; o <<= 1) {
@@ -61,7 +62,7 @@ __device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wav
     if (lane == kWave - 1) s_wave[w] = x;
     __syncthreads();
     int64_t pre = 0, tot = 0;
-    for (int i = 0; i < kDWaves; ++i) {
+    for (int i = 0; i < NW; ++i) {
         if (i < w) pre += s_wave[i];
         tot += s_wave[i];
     }
@@ -71,7 +72,12 @@ __device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wav
 
 template <int W>
 __device__ __forceinline__ uint32_t digit_of(const Key<W> &k, int shift) {
-    return (uint32_t)(k.w[shift >> 6] >> (shift & 63)) & 0xffu;
+    // 8-bit digits never straddle a word; the word is selected with static indices
+    uint64_t v = k.w[0];
+#pragma unroll
+    for (int j = 1; j < W; ++j)
+        if ((shift >> 6) == j) v = k.w[j];
+    return (uint32_t)(v >> (shift & 63)) & 0xffu;
 }
 
 // number of low bits in which keys may differ, given the OR of (key ^ key0)
@@ -814,16 +820,22 @@ __device__ __forceinline__ void wave_scan256(const uint32_t tot[4], uint32_t pre
     }
 }
 
+// The bucket kernel runs 512-thread workgroups: its LDS allows two workgroups
+// per CU, and the extra waves hide LDS and memory latency.
+constexpr int kBThreads = 512;
+constexpr int kBWaves = kBThreads / kWave;
+
 template <int W>
-__global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
+__global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
+    constexpr int kBK = C::CAP / kBThreads;  // keys per thread at capacity
     __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
     __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
     __shared__ uint16_t s_rank[C::CAP];      // per-key rank within its wave and digit
-    __shared__ uint32_t s_cnt[kDWaves][256]; // per-wave digit counts, then that wave's output offsets
+    __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];  // per-wave digit counts, then output offsets
     __shared__ uint64_t s_or[2];
-    __shared__ int s_u[kDWaves];
-    __shared__ int64_t s_wsum[kDWaves];
+    __shared__ int s_u[kBWaves];
+    __shared__ int64_t s_wsum[kBWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t s = blockIdx.x;  // unit
     if (s >= *a.n_units) return;
@@ -843,20 +855,20 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
     if (size > 0) {
         const int m = (int)size;
         // each wave owns a contiguous slice of CHm positions
-        const int Km = (m + kDThreads - 1) / kDThreads;
+        const int Km = (m + kBThreads - 1) / kBThreads;
         const int CHm = Km * kWave;
         const int my0 = w * CHm;
         {
             // every load in flight before the first LDS store
-            Key<W> tmp[C::K];
+            Key<W> tmp[kBK];
 #pragma unroll
-            for (int k = 0; k < C::K; ++k) {
-                const int i = k * kDThreads + threadIdx.x;
+            for (int k = 0; k < kBK; ++k) {
+                const int i = k * kBThreads + threadIdx.x;
                 if (i < m) tmp[k] = load_key<W>(a.src, start + i);
             }
 #pragma unroll
-            for (int k = 0; k < C::K; ++k) {
-                const int i = k * kDThreads + threadIdx.x;
+            for (int k = 0; k < kBK; ++k) {
+                const int i = k * kBThreads + threadIdx.x;
                 if (i < m) s_k0[i] = tmp[k];
             }
         }
@@ -865,7 +877,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
         while ((1 << log_t) < 2 * m) ++log_t;
         const uint32_t tmask = (1u << log_t) - 1u;
         uint32_t *tab = reinterpret_cast<uint32_t *>(s_k1);
-        for (int i = threadIdx.x; i < (1 << log_t) / 2; i += kDThreads) tab[i] = 0xffffffffu;
+        for (int i = threadIdx.x; i < (1 << log_t) / 2; i += kBThreads) tab[i] = 0xffffffffu;
         if (threadIdx.x == 0) s_or[0] = s_or[1] = 0;
         __syncthreads();
         const Key<W> ref = s_k0[0];
@@ -924,13 +936,13 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
         const int nbits = varying_bits<W>(orx);
         int u = 0;
 #pragma unroll
-        for (int ww = 0; ww < kDWaves; ++ww) u += s_u[ww];
+        for (int ww = 0; ww < kBWaves; ++ww) u += s_u[ww];
 
         // stable LSD radix sort of the u unique keys, LDS resident.  The first pass
         // reads every wave's own slice (any starting order is fine); later passes
         // read the contiguous result of the previous pass.
         Key<W> *cur = s_k0, *nxt = s_k1;
-        const int Kd = (u + kDThreads - 1) / kDThreads;
+        const int Kd = (u + kBThreads - 1) / kBThreads;
         const int CHd = Kd * kWave;
         bool first = true;
         for (int shift = 0; shift < nbits; shift += 8) {
@@ -946,30 +958,32 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
                 const int tot = wave_match_rank_skip(d, valid, &rk);
                 uint32_t base = 0;
                 if (valid) base = s_cnt[w][d];
-                if (valid && rk == 0) s_cnt[w][d] = base + (uint32_t)tot;
+                if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
                 if (valid) s_rank[pos] = (uint16_t)(base + (uint32_t)rk);
             }
             __syncthreads();
             // this wave's output offset per digit: all keys of smaller digits, plus
             // keys of this digit held by lower waves (each wave computes its own row)
-            uint32_t tot[4], pre[4], low[4];
+            // (each lane holds digits 4*lane .. 4*lane+3: one 8-byte LDS read per wave row)
+            uint32_t tot[4] = {0u, 0u, 0u, 0u}, pre[4], low[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int d = 4 * lane + j;
-                uint32_t t = 0, l = 0;
+            for (int ww = 0; ww < kBWaves; ++ww) {
+                const uint64_t c4 = *reinterpret_cast<const uint64_t *>(&s_cnt[ww][4 * lane]);
 #pragma unroll
-                for (int ww = 0; ww < kDWaves; ++ww) {
-                    const uint32_t c = s_cnt[ww][d];
-                    t += c;
-                    l += (ww < w) ? c : 0u;
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t c = (uint32_t)(c4 >> (16 * j)) & 0xffffu;
+                    tot[j] += c;
+                    low[j] += (ww < w) ? c : 0u;
                 }
-                tot[j] = t;
-                low[j] = l;
             }
             wave_scan256(tot, pre);
             __syncthreads();  // every wave has read the counts before rows are overwritten
+            {
+                uint64_t o4 = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) s_cnt[w][4 * lane + j] = pre[j] + low[j];
+                for (int j = 0; j < 4; ++j) o4 |= (uint64_t)((pre[j] + low[j]) & 0xffffu) << (16 * j);
+                *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = o4;
+            }
             for (int k = 0; k < rounds; ++k) {
                 const int pos = base_pos + k * kWave + lane;
                 if (pos < limit) {
@@ -986,7 +1000,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
         if (first) {
             // no pass ran: every unique key is equal, so there is exactly one
             if (threadIdx.x == 0) {
-                for (int ww = 0; ww < kDWaves; ++ww)
+                for (int ww = 0; ww < kBWaves; ++ww)
                     if (s_u[ww] > 0) {
                         s_k1[0] = s_k0[ww * CHm];
                         break;
@@ -997,7 +1011,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
         }
         // the sorted unique run to the bucket's offset; set hits for the union count
         int64_t hit = 0;
-        for (int i = threadIdx.x; i < u; i += kDThreads) {
+        for (int i = threadIdx.x; i < u; i += kBThreads) {
             const Key<W> key = cur[i];
             store_key<W>(a.dst, start + i, key);
             if (bh > bl && contains_set<W>(a.B, bl, bh, key)) ++hit;
@@ -1005,7 +1019,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_kernel(BucketArgs a) {
         nu = u;
         if (bh > bl) {
             int64_t ht;
-            block_excl_scan_i64(hit, &ht, s_wsum);
+            block_excl_scan_i64<kBWaves>(hit, &ht, s_wsum);
             matches = ht;
         }
     }
@@ -1459,7 +1473,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     b.n_big = scal + 3;
     b.big = (int64_t *)(ws + L.big);
     SCI_HIP_TRY(launch_set_i64(b.n_big, 0, st));
-    SCI_LAUNCH(bucket_kernel<W>, dim3((unsigned)b.n_slots), dim3(kDThreads), 0, st, b);
+    SCI_LAUNCH(bucket_kernel<W>, dim3((unsigned)b.n_slots), dim3(kBThreads), 0, st, b);
     SCI_LAUNCH(bucket_big_kernel<W>, dim3(4096), dim3(kDThreads), 0, st, b);
     SCI_HIP_TRY(hipGetLastError());
     SCI_HIP_TRY(device_scan(b.ucount, scal + 5, b.n_slots + 1, sums, scal + 0, st));

@@ -44,9 +44,13 @@ __device__ __forceinline__ int lowest_bit(const Key<W> &k) {
     return -1;
 }
 
+// static word indexing keeps the key in registers (a runtime index would put it in scratch)
 template <int W>
 __device__ __forceinline__ void clear_bit(Key<W> &k, int b) {
-    k.w[b >> 6] &= ~(1ull << (b & 63));
+    const uint64_t m = ~(1ull << (b & 63));
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if ((b >> 6) == j) k.w[j] &= m;
 }
 
 // <bra|H|ket> for bra = ket with one or two electrons moved (x = bra ^ ket, pc = popcount(x))
@@ -137,11 +141,49 @@ __device__ double diag_elem(const EnergyArgs &a, const Key<W> &d) {
 // Off-diagonal part of (H psi)_i for the rows of blockIdx.x against the
 // columns of column block blockIdx.y; the partial sum goes to
 // partial_rows[blockIdx.y][i] (combined in a fixed order by hpsi_finish_kernel).
+// Connected pairs found by a wave wait in a per-wave LDS queue, in ascending
+// column order, and are evaluated 64 at a time with every lane busy (one
+// entry per lane, the row's determinant fetched from its owner lane); each row
+// lane then adds its own entries in queue order, so every row still sums its
+// terms in ascending j.
+constexpr int kQueue = 2 * kWave;
+
+template <int W>
+__device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &di, int n_q, const uint32_t *q_ent,
+                                           double *q_val, const Key<W> *tile_keys, const double *tile_psi,
+                                           double &acc) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int base = 0; base < n_q; base += kWave) {
+        const int k = base + lane;
+        const uint32_t e = k < n_q ? q_ent[k] : 0u;
+        const int r = (int)(e >> 16);
+        Key<W> bra;
+#pragma unroll
+        for (int j = 0; j < W; ++j) bra.w[j] = __shfl(di.w[j], r);
+        if (k < n_q) {
+            const int t = (int)(e & 0x3ffu);
+            const int pc = (e >> 15) & 1u ? 4 : 2;
+            const Key<W> ket = tile_keys[t];
+            Key<W> x;
+#pragma unroll
+            for (int j = 0; j < W; ++j) x.w[j] = bra.w[j] ^ ket.w[j];
+            q_val[k] = offdiag_elem<W>(a, bra, ket, x, pc) * tile_psi[t];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < n_q; ++k)
+        if ((int)(q_ent[k] >> 16) == lane) acc += q_val[k];
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int W>
 __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
     __shared__ Key<W> tile_keys[kColTile];
     __shared__ double tile_psi[kColTile];
+    __shared__ uint32_t s_ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | (four moved << 15) | column
+    __shared__ double s_val[kRowThreads / kWave][kQueue];
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t i = (int64_t)blockIdx.x * kRowThreads + tid;
     const bool active = i < a.n_sel;
     Key<W> di;
@@ -158,6 +200,8 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
                 atomicOr(a.flags, SCI_FLAG_UNSORTED);
         }
     }
+    uint32_t *q_ent = s_ent[w];
+    double *q_val = s_val[w];
     const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)gridDim.y), (int64_t)kColTile) * kColTile;
     const int64_t c0 = (int64_t)blockIdx.y * per;
     const int64_t c1 = min<int64_t>(c0 + per, a.n_sel);
@@ -186,15 +230,29 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
             }
         }
         __syncthreads();
-        if (active) {
-            for (int t = 0; t < cnt; ++t) {
-                const Key<W> dj = tile_keys[t];
-                Key<W> x;
+        int n_q = 0;  // wave-uniform
+        for (int t = 0; t < cnt; ++t) {
+            const Key<W> dj = tile_keys[t];
+            Key<W> x;
 #pragma unroll
-                for (int j = 0; j < W; ++j) x.w[j] = di.w[j] ^ dj.w[j];
-                const int pc = key_popc<W>(x);
-                if (pc == 2 || pc == 4) acc += offdiag_elem<W>(a, di, dj, x, pc) * tile_psi[t];
+            for (int j = 0; j < W; ++j) x.w[j] = di.w[j] ^ dj.w[j];
+            const int pc = key_popc<W>(x);
+            const bool conn = active && (pc == 2 || pc == 4);
+            const uint64_t bal = __ballot(conn);
+            if (bal == 0ull) continue;
+            if (conn)
+                q_ent[n_q + __popcll(bal & lanemask_lt())] =
+                    ((uint32_t)lane << 16) | ((uint32_t)(pc == 4) << 15) | (uint32_t)t;
+            n_q += __popcll(bal);
+            if (n_q >= kWave) {
+                __builtin_amdgcn_wave_barrier();
+                flush_queue<W>(a, di, n_q, q_ent, q_val, tile_keys, tile_psi, acc);
+                n_q = 0;
             }
+        }
+        if (n_q > 0) {
+            __builtin_amdgcn_wave_barrier();
+            flush_queue<W>(a, di, n_q, q_ent, q_val, tile_keys, tile_psi, acc);
         }
     }
     if (active) a.partial_rows[(int64_t)blockIdx.y * a.n_sel + i] = acc;
