@@ -486,7 +486,9 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
 // Scatter pass: each key to its bucket's range (order inside a bucket is free).
 template <int W, int FMAX>
 __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
-    __shared__ unsigned long long s_run[FMAX];
+    // each bucket's output base for this tile, and a 32-bit cursor (a tile holds < 2^32 keys)
+    __shared__ int64_t s_base[FMAX];
+    __shared__ uint32_t s_off[FMAX];
     const int64_t g = blockIdx.x;
     if (g >= a.tile_base[a.S_in]) return;
     const int s = find_segment(a.tile_base, a.S_in, g);
@@ -496,7 +498,10 @@ __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
     const int64_t start = a.seg_in[s] + t * a.tile;
     const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
     const int64_t *cp = a.counts + a.cbase[s];
-    for (int j = threadIdx.x; j < f; j += kDThreads) s_run[j] = (unsigned long long)cp[(int64_t)j * T + t];
+    for (int j = threadIdx.x; j < f; j += kDThreads) {
+        s_base[j] = cp[(int64_t)j * T + t];
+        s_off[j] = 0u;
+    }
     __syncthreads();
     constexpr int U = 8;
     for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kDThreads) {
@@ -514,8 +519,8 @@ __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (b[u] >= 0) {
-                const unsigned long long pos = atomicAdd(&s_run[b[u]], 1ull);
-                store_key<W>(a.out, (int64_t)pos, k[u]);
+                const uint32_t o = atomicAdd(&s_off[b[u]], 1u);
+                store_key<W>(a.out, s_base[b[u]] + (int64_t)o, k[u]);
             }
         }
     }
@@ -828,7 +833,7 @@ constexpr int kBWaves = kBThreads / kWave;
 template <int W>
 __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
-    constexpr int kBK = C::CAP / kBThreads;  // keys per thread at capacity
+    constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
     __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
     __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
     __shared__ uint16_t s_rank[C::CAP];      // per-key rank within its wave and digit
