@@ -43,6 +43,8 @@ def parse():
                     help="skip the large-workload streaming and energy/autograd timings")
     ap.add_argument("--large-sources", type=int, default=4096)
     ap.add_argument("--large-chunk", type=int, default=1 << 28)
+    ap.add_argument("--batch-chunks", type=int, default=32,
+                    help="chunks of the batched workload (each one batch over all systems)")
     return ap.parse_args()
 
 
@@ -106,6 +108,105 @@ def select_extras(torch, sci, keys, n_cand, union, n_union_dev, n_union, sel, n_
     t_ms = _median_ms(run, 3, torch)
     out["topk"] = {"n": nn, "k": K, "ms": t_ms, "entries_per_s": nn / (t_ms / 1000.0), "n_selected": int(n_out.item())}
     return out
+
+
+def batch_extras(args, torch, sci, si):
+    """The batched workload (64 systems of uneven size, both key widths): full
+    generation of every system, cut into chunks that each cover a slice of every
+    system, as batched launches, as one captured graph replayed, and as 64
+    sequential plain calls per chunk; energies of all 64 systems batched vs plain."""
+    wls = si.batch_workloads()
+    systems = [si.make_system(w) for w in wls]
+    dev = torch.device("cuda", 0)
+    hams = [sci.Ham(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri) for s in systems]
+    sels = [sci.keys_to_device(s.dets) for s in systems]
+    E = [s.dets.shape[0] * h.n_coupled for s, h in zip(systems, hams)]
+    total = sum(E)
+    K = args.batch_chunks
+    rng = [[(j * e // K, (j + 1) * e // K) for e in E] for j in range(K)]
+    words = max(sum((r1 - r0) * h.W for (r0, r1), h in zip(rng[j], hams)) for j in range(K))
+    cmax = max(sum(r1 - r0 for r0, r1 in rng[j]) for j in range(K))
+    pool_k = torch.empty(words + 1, dtype=torch.int64, device=dev)
+    pool_h = torch.empty(cmax + 1, dtype=torch.float64, device=dev)
+    flags = sci.new_flags(dev)
+
+    def views(j):
+        out, ok, oh = [], 0, 0
+        for (r0, r1), h in zip(rng[j], hams):
+            n = r1 - r0
+            out.append((pool_k[ok: ok + n * h.W].view(n, h.W), pool_h[oh: oh + n]))
+            ok += n * h.W
+            oh += n
+        return out
+
+    def items(j):
+        return [(h, d, r0, r1, kv, hv) for h, d, (r0, r1), (kv, hv) in zip(hams, sels, rng[j], views(j))]
+
+    first = sci.GenBatch(items(0), flags=flags)
+    tile = first.autotune()
+    batches = [first] + [sci.GenBatch(items(j), tile_candidates=tile, flags=flags) for j in range(1, K)]
+    torch.cuda.synchronize()
+
+    def run_batched():
+        for b in batches:
+            b.launch()
+
+    all_views = [views(j) for j in range(K)]
+
+    def run_plain():
+        for k, (h, d) in enumerate(zip(hams, sels)):
+            for j in range(K):
+                r0, r1 = rng[j][k]
+                kv, hv = all_views[j][k]
+                sci.sci_gen_coupled(h, d, d.shape[0], r0, r1, -1.0, kv, hv, None, r1 - r0, None, flags)
+
+    run_batched()
+    run_plain()
+    torch.cuda.synchronize()
+    b_ms = _median_ms(run_batched, 3, torch)
+    p_ms = _median_ms(run_plain, 3, torch)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            run_batched()
+    torch.cuda.synchronize()
+    g_ms = _median_ms(graph.replay, 3, torch)
+    sci.check_flags(flags, "batched generation")
+    del graph
+    gen = {"workload": f"{len(wls)} systems (n_orb {min(w.n_orb for w in wls)}-{max(w.n_orb for w in wls)}, "
+                       f"{sum(w.W == 2 for w in wls)} with W=2, {sum(w.n_sel for w in wls)} selected dets), "
+                       f"full generation in {K} chunks",
+           "n_candidates": total, "tile_candidates": tile,
+           "batched_ms": b_ms, "graph_ms": g_ms, "sequential_plain_ms": p_ms,
+           "batched_candidates_per_s": total / (b_ms / 1000.0), "graph_candidates_per_s": total / (g_ms / 1000.0),
+           "sequential_candidates_per_s": total / (p_ms / 1000.0), "speedup_vs_sequential": p_ms / b_ms}
+    for b in batches:
+        b.close()
+    del pool_k, pool_h
+    # energies (with gradients) of all systems
+    psis = [torch.from_numpy(s.psi).to(dev) for s in systems]
+    eb = sci.EnergyBatch([(h, d, p) for h, d, p in zip(hams, sels, psis)], flags=flags)
+    outs = [(torch.zeros(1, dtype=torch.float64, device=dev), torch.empty(d.shape[0], dtype=torch.float64, device=dev),
+             torch.empty(d.shape[0], dtype=torch.float64, device=dev),
+             torch.empty(sci.sci_energy_workspace_bytes(d.shape[0]), dtype=torch.uint8, device=dev)) for d in sels]
+
+    def plain_energy():
+        for h, d, p, (e, hp, g, ws) in zip(hams, sels, psis, outs):
+            sci.sci_energy(h, d, d.shape[0], p, e, hp, g, ws, ws.numel(), flags)
+
+    eb.launch()
+    plain_energy()
+    torch.cuda.synchronize()
+    same = all(eb.energy[k].item() == outs[k][0].item() for k in range(len(outs)))
+    eb_ms = _median_ms(eb.launch, 5, torch)
+    ep_ms = _median_ms(plain_energy, 5, torch)
+    sci.check_flags(flags, "batched energy")
+    eb.close()
+    en = {"workload": f"E and dE/dpsi of all {len(wls)} systems", "batched_ms": eb_ms, "sequential_plain_ms": ep_ms,
+          "speedup_vs_sequential": ep_ms / eb_ms, "bit_identical_to_plain": same}
+    return gen, en
 
 
 def large_extras(args, torch, sci, si):
@@ -371,6 +472,9 @@ def main():
         torch.cuda.empty_cache()
         ls, eg = large_extras(args, torch, sci, si)
         result["extras"].update({"large_stream": ls, "energy_grad_large": eg})
+        torch.cuda.empty_cache()
+        bg, be = batch_extras(args, torch, sci, si)
+        result["extras"].update({"batched_generation": bg, "batched_energy": be})
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, args.cpu_sources)
     print(json.dumps(result), flush=True)

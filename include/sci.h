@@ -126,6 +126,45 @@ int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
                         sci_stream_t stream);
 
 /*
+ * Batched generation (several systems, one persistent launch; paper section
+ * 4.2: the grid-stride virtual-thread loop over all work, here over the
+ * sources of every system of the batch).
+ *
+ * sci_gen_item describes one system's dense-mode call, exactly as
+ * sci_gen_coupled with eps < 0: the excitation range [exc_begin, exc_end) of
+ * dets (device [n_dets][W]) is written to out_keys (device
+ * [exc_end - exc_begin][W]) and out_hij (device [exc_end - exc_begin]).
+ * Items may mix key widths and may alias nothing they write.
+ *
+ * sci_gen_batch_create: validates every item (as sci_gen_coupled would) and
+ * uploads the item table and a tile list (runs of consecutive sources of
+ * about tile_candidates candidates, largest first) to device memory owned by
+ * the handle; device-detected conditions set bits in dev_flags.  Synchronous.
+ * sci_gen_coupled_batched: one launch over every tile of the batch on
+ * `stream`: it allocates nothing and never synchronises, so it can be
+ * captured in a graph.  One launch of a given batch at a time.
+ * sci_gen_batch_autotune: times the batch with several tile sizes, keeps the
+ * fastest and returns it in *tile_candidates (nullable).  Synchronous; it
+ * writes the outputs (with their correct values).
+ * Errors: SCI_EINVAL, SCI_EUNSUPPORTED, SCI_ENOMEM, SCI_EHIP.
+ */
+typedef struct sci_gen_item {
+    sci_ham_t ham;
+    const uint64_t *dets;
+    int64_t n_dets;
+    int64_t exc_begin, exc_end;
+    uint64_t *out_keys;
+    double *out_hij;
+} sci_gen_item;
+typedef struct sci_gen_batch_s *sci_gen_batch_t;
+
+int32_t sci_gen_batch_create(const sci_gen_item *items, int32_t n_items, int64_t tile_candidates,
+                             uint32_t *dev_flags, sci_gen_batch_t *out);
+int32_t sci_gen_batch_destroy(sci_gen_batch_t batch);
+int32_t sci_gen_coupled_batched(sci_gen_batch_t batch, sci_stream_t stream);
+int32_t sci_gen_batch_autotune(sci_gen_batch_t batch, sci_stream_t stream, int64_t *tile_candidates);
+
+/*
  * Workspace bytes sci_dedup_merge needs for n_cand candidates of W words.
  */
 size_t sci_dedup_workspace_bytes(int32_t n_words, int64_t n_cand);
@@ -179,6 +218,33 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
                    double *energy, double *h_psi, double *grad,
                    void *workspace, size_t workspace_bytes,
                    uint32_t *dev_flags, sci_stream_t stream);
+
+/*
+ * Batched energy (several systems; the per-block work of sci_energy over tile
+ * lists covering every system, a handful of launches in all).  Each item is
+ * one sci_energy call (sel strictly ascending, psi, energy required; h_psi and
+ * grad nullable), and each system's results are bit-identical to that call.
+ * sci_energy_batch_create validates the items, uploads the tile lists and
+ * allocates each system's workspace (owned by the handle); synchronous.
+ * sci_energy_batched enqueues the work on `stream`; it allocates nothing and
+ * never synchronises.  One launch of a given batch at a time.
+ * Errors: SCI_EINVAL, SCI_EUNSUPPORTED, SCI_ENOMEM, SCI_EHIP.
+ */
+typedef struct sci_energy_item {
+    sci_ham_t ham;
+    const uint64_t *sel;
+    int64_t n_sel;
+    const double *psi;
+    double *energy;
+    double *h_psi;
+    double *grad;
+} sci_energy_item;
+typedef struct sci_energy_batch_s *sci_energy_batch_t;
+
+int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t n_items, uint32_t *dev_flags,
+                                sci_energy_batch_t *out);
+int32_t sci_energy_batch_destroy(sci_energy_batch_t batch);
+int32_t sci_energy_batched(sci_energy_batch_t batch, sci_stream_t stream);
 
 /*
  * Streaming generation + de-duplication through a device pool (paper

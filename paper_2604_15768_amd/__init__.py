@@ -73,6 +73,30 @@ _lib.sci_topk_workspace_bytes.argtypes = [_i64]
 _lib.sci_topk_workspace_bytes.restype = _sz
 _lib.sci_topk.argtypes = [_i32, _P, _P, _i64, _i64, _P, _P, _P, _i64, _P, _sz, _P, _P]
 _lib.sci_topk.restype = _i32
+class SciGenItem(ctypes.Structure):
+    _fields_ = [("ham", _P), ("dets", _P), ("n_dets", _i64), ("exc_begin", _i64), ("exc_end", _i64),
+                ("out_keys", _P), ("out_hij", _P)]
+
+
+_lib.sci_gen_batch_create.argtypes = [ctypes.POINTER(SciGenItem), _i32, _i64, _P, ctypes.POINTER(_P)]
+_lib.sci_gen_batch_create.restype = _i32
+_lib.sci_gen_batch_destroy.argtypes = [_P]
+_lib.sci_gen_batch_destroy.restype = _i32
+_lib.sci_gen_coupled_batched.argtypes = [_P, _P]
+_lib.sci_gen_coupled_batched.restype = _i32
+_lib.sci_gen_batch_autotune.argtypes = [_P, _P, ctypes.POINTER(_i64)]
+_lib.sci_gen_batch_autotune.restype = _i32
+class SciEnergyItem(ctypes.Structure):
+    _fields_ = [("ham", _P), ("sel", _P), ("n_sel", _i64), ("psi", _P), ("energy", _P), ("h_psi", _P),
+                ("grad", _P)]
+
+
+_lib.sci_energy_batch_create.argtypes = [ctypes.POINTER(SciEnergyItem), _i32, _P, ctypes.POINTER(_P)]
+_lib.sci_energy_batch_create.restype = _i32
+_lib.sci_energy_batch_destroy.argtypes = [_P]
+_lib.sci_energy_batch_destroy.restype = _i32
+_lib.sci_energy_batched.argtypes = [_P, _P]
+_lib.sci_energy_batched.restype = _i32
 _lib.sci_profile_enable.argtypes = [_i32]
 _lib.sci_profile_enable.restype = _i32
 _lib.sci_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), _i32]
@@ -375,6 +399,93 @@ def topk(keys: torch.Tensor, psi: torch.Tensor, k: int, W: int, flags=None):
         flags = new_flags(dev)
     sci_topk(W, keys, psi, n, k, out_keys, out_psi, n_out, kk, ws, ws.numel(), flags)
     return out_keys, out_psi, n_out, flags
+
+
+class GenBatch:
+    """A batch of dense-mode generation calls over several systems, run as one
+    persistent launch per key width (sci_gen_batch_create / sci_gen_coupled_batched).
+
+    items: (ham, dets, exc_begin, exc_end, out_keys, out_hij) tuples; the tensors
+    are kept alive by the batch."""
+
+    def __init__(self, items, tile_candidates=1 << 18, flags=None):
+        arr = (SciGenItem * max(len(items), 1))()
+        keep = []
+        dev = None
+        for i, (ham, dets, e0, e1, keys, hij) in enumerate(items):
+            arr[i] = SciGenItem(ham.handle.value, dets.data_ptr(), dets.shape[0], e0, e1, keys.data_ptr(),
+                                hij.data_ptr())
+            keep += [ham, dets, keys, hij]
+            dev = dets.device
+        self.flags = flags if flags is not None else new_flags(dev if dev is not None else "cuda")
+        h = _P()
+        _check(_lib.sci_gen_batch_create(arr, len(items), int(tile_candidates), _ptr(self.flags), ctypes.byref(h)),
+               "sci_gen_batch_create")
+        self._h = h
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(_lib.sci_gen_coupled_batched(self._h, _stream(stream)), "sci_gen_coupled_batched")
+
+    def autotune(self, stream=None) -> int:
+        tc = _i64(0)
+        _check(_lib.sci_gen_batch_autotune(self._h, _stream(stream), ctypes.byref(tc)), "sci_gen_batch_autotune")
+        return int(tc.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            _lib.sci_gen_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EnergyBatch:
+    """Energies (and optionally H psi and gradients) of several systems in a few
+    launches (sci_energy_batch_create / sci_energy_batched).
+
+    items: (ham, sel, psi) tuples.  Outputs are allocated here: `energy` [n_items],
+    `h_psi` and `grad` lists of per-system tensors."""
+
+    def __init__(self, items, want_grad=True, flags=None):
+        arr = (SciEnergyItem * len(items))()
+        dev = items[0][1].device
+        self.energy = torch.zeros(len(items), dtype=torch.float64, device=dev)
+        self.h_psi, self.grad, keep = [], [], []
+        for i, (ham, sel, psi) in enumerate(items):
+            hp = torch.empty(sel.shape[0], dtype=torch.float64, device=dev)
+            g = torch.empty(sel.shape[0], dtype=torch.float64, device=dev) if want_grad else None
+            self.h_psi.append(hp)
+            self.grad.append(g)
+            arr[i] = SciEnergyItem(ham.handle.value, sel.data_ptr(), sel.shape[0], psi.data_ptr(),
+                                   self.energy[i:].data_ptr(), hp.data_ptr(), g.data_ptr() if g is not None else None)
+            keep += [ham, sel, psi]
+        self.flags = flags if flags is not None else new_flags(dev)
+        h = _P()
+        _check(_lib.sci_energy_batch_create(arr, len(items), _ptr(self.flags), ctypes.byref(h)),
+               "sci_energy_batch_create")
+        self._h = h
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(_lib.sci_energy_batched(self._h, _stream(stream)), "sci_energy_batched")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            _lib.sci_energy_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SciEnergy(torch.autograd.Function):

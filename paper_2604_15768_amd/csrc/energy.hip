@@ -13,6 +13,9 @@
 // the same integral tables the generation kernel uses; H_ij is never stored.
 // Row sums run in ascending j, block sums in a fixed tree, so repeated calls
 // are bit-identical.
+#include <algorithm>
+#include <vector>
+
 #include "sci_internal.hpp"
 
 namespace sci {
@@ -177,14 +180,21 @@ __device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &d
 }
 
 template <int W>
-__global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
-    __shared__ Key<W> tile_keys[kColTile];
-    __shared__ double tile_psi[kColTile];
-    __shared__ uint32_t s_ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | (four moved << 15) | column
-    __shared__ double s_val[kRowThreads / kWave][kQueue];
+struct HpsiLds {
+    Key<W> tile_keys[kColTile];
+    double tile_psi[kColTile];
+    uint32_t ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | (four moved << 15) | column
+    double val[kRowThreads / kWave][kQueue];
+};
+
+// rows [rb*256, rb*256+256) against column block cb of n_col
+template <int W>
+__device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int cb, int n_col, HpsiLds<W> &S) {
+    Key<W> *tile_keys = S.tile_keys;
+    double *tile_psi = S.tile_psi;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), w = tid / kWave;
-    const int64_t i = (int64_t)blockIdx.x * kRowThreads + tid;
+    const int64_t i = rb * kRowThreads + tid;
     const bool active = i < a.n_sel;
     Key<W> di;
 #pragma unroll
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
     double acc = 0.0;
     if (active) {
         di = load_key<W>(a.sel, i);
-        if (blockIdx.y == 0) {
+        if (cb == 0) {
             int na, nb;
             spin_popc<W>(di, a.n, na, nb);
             if (na != a.na || nb != a.nb || key_popc<W>(di) != na + nb) atomicOr(a.flags, SCI_FLAG_BAD_DET);
@@ -200,10 +210,10 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
                 atomicOr(a.flags, SCI_FLAG_UNSORTED);
         }
     }
-    uint32_t *q_ent = s_ent[w];
-    double *q_val = s_val[w];
-    const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)gridDim.y), (int64_t)kColTile) * kColTile;
-    const int64_t c0 = (int64_t)blockIdx.y * per;
+    uint32_t *q_ent = S.ent[w];
+    double *q_val = S.val[w];
+    const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)n_col), (int64_t)kColTile) * kColTile;
+    const int64_t c0 = (int64_t)cb * per;
     const int64_t c1 = min<int64_t>(c0 + per, a.n_sel);
     for (int64_t j0 = c0; j0 < c1; j0 += kColTile) {
         const int cnt = (int)min<int64_t>(kColTile, c1 - j0);
@@ -255,13 +265,19 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
             flush_queue<W>(a, di, n_q, q_ent, q_val, tile_keys, tile_psi, acc);
         }
     }
-    if (active) a.partial_rows[(int64_t)blockIdx.y * a.n_sel + i] = acc;
+    if (active) a.partial_rows[(int64_t)cb * a.n_sel + i] = acc;
+}
+
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
+    __shared__ HpsiLds<W> S;
+    hpsi_tile<W>(a, blockIdx.x, blockIdx.y, gridDim.y, S);
 }
 
 // (H psi)_i = H_ii psi_i + the column-block partial sums in block order
 template <int W>
-__global__ __launch_bounds__(kRowThreads) void hpsi_finish_kernel(EnergyArgs a, int n_col) {
-    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+__device__ __forceinline__ void hpsi_finish_rows(const EnergyArgs &a, int64_t rb, int n_col) {
+    const int64_t i = rb * kRowThreads + threadIdx.x;
     if (i >= a.n_sel) return;
     double acc = 0.0;
     for (int c = 0; c < n_col; ++c) acc += a.partial_rows[(int64_t)c * a.n_sel + i];
@@ -269,12 +285,16 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_finish_kernel(EnergyArgs a, 
     a.hpsi[i] = diag_elem<W>(a, di) * a.psi[i] + acc;
 }
 
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_finish_kernel(EnergyArgs a, int n_col) {
+    hpsi_finish_rows<W>(a, blockIdx.x, n_col);
+}
+
 // per-block partial sums of psi_i*(H psi)_i and psi_i^2, fixed tree order
-__global__ __launch_bounds__(kRedThreads) void reduce_partial_kernel(EnergyArgs a) {
-    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+__device__ __forceinline__ void reduce_partial_block(const EnergyArgs &a, int64_t blk, double *s_num, double *s_den) {
     const int tid = threadIdx.x;
     const int64_t per_block = (int64_t)kRedThreads * 8;
-    const int64_t base = (int64_t)blockIdx.x * per_block;
+    const int64_t base = blk * per_block;
     double num = 0.0, den = 0.0;
     for (int k = 0; k < 8; ++k) {
         const int64_t i = base + (int64_t)k * kRedThreads + tid;
@@ -295,13 +315,17 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partial_kernel(EnergyArgs 
         __syncthreads();
     }
     if (tid == 0) {
-        a.partial[2 * blockIdx.x] = s_num[0];
-        a.partial[2 * blockIdx.x + 1] = s_den[0];
+        a.partial[2 * blk] = s_num[0];
+        a.partial[2 * blk + 1] = s_den[0];
     }
 }
 
-__global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(EnergyArgs a, int n_blocks) {
+__global__ __launch_bounds__(kRedThreads) void reduce_partial_kernel(EnergyArgs a) {
     __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    reduce_partial_block(a, blockIdx.x, s_num, s_den);
+}
+
+__device__ __forceinline__ void reduce_final_all(const EnergyArgs &a, int n_blocks, double *s_num, double *s_den) {
     const int tid = threadIdx.x;
     double num = 0.0, den = 0.0;
     for (int b = tid; b < n_blocks; b += kRedThreads) {
@@ -325,12 +349,18 @@ __global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(EnergyArgs a,
     }
 }
 
-__global__ void grad_kernel(EnergyArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(EnergyArgs a, int n_blocks) {
+    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    reduce_final_all(a, n_blocks, s_num, s_den);
+}
+
+__device__ __forceinline__ void grad_rows(const EnergyArgs &a, int64_t i) {
     if (i >= a.n_sel) return;
     const double e = a.energy[0], den = a.scalars[1];
     a.grad[i] = 2.0 * (a.hpsi[i] - e * a.psi[i]) / den;
 }
+
+__global__ void grad_kernel(EnergyArgs a) { grad_rows(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x); }
 
 static int64_t reduce_blocks(int64_t n_sel) { return std::max<int64_t>(1, ceil_div(n_sel, (int64_t)kRedThreads * 8)); }
 
@@ -409,5 +439,186 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
         SCI_LAUNCH(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
         SCI_HIP_TRY(hipGetLastError());
     }
+    return SCI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of systems: the same per-block work as sci_energy, over tile lists
+// that cover every system, so each system's results are bit-identical to its
+// own sci_energy call
+// ---------------------------------------------------------------------------
+
+namespace sci {
+
+struct EnergyTile {
+    int32_t item;
+    int32_t cb;  // column block (H psi tiles)
+    int64_t rb;  // row block of 256 (H psi, finish, gradient) or reduction block
+};
+
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_batched_kernel(const EnergyArgs *__restrict__ items,
+                                                                   const int32_t *__restrict__ ncol,
+                                                                   const EnergyTile *__restrict__ tiles) {
+    __shared__ HpsiLds<W> S;
+    const EnergyTile t = tiles[blockIdx.x];
+    hpsi_tile<W>(items[t.item], t.rb, t.cb, ncol[t.item], S);
+}
+
+template <int W>
+__global__ __launch_bounds__(kRowThreads) void hpsi_finish_batched_kernel(const EnergyArgs *__restrict__ items,
+                                                                          const int32_t *__restrict__ ncol,
+                                                                          const EnergyTile *__restrict__ rows) {
+    const EnergyTile t = rows[blockIdx.x];
+    hpsi_finish_rows<W>(items[t.item], t.rb, ncol[t.item]);
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_partial_batched_kernel(const EnergyArgs *__restrict__ items,
+                                                                             const EnergyTile *__restrict__ blocks) {
+    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    const EnergyTile t = blocks[blockIdx.x];
+    reduce_partial_block(items[t.item], t.rb, s_num, s_den);
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_final_batched_kernel(const EnergyArgs *__restrict__ items,
+                                                                           const int32_t *__restrict__ n_blocks) {
+    __shared__ double s_num[kRedThreads], s_den[kRedThreads];
+    reduce_final_all(items[blockIdx.x], n_blocks[blockIdx.x], s_num, s_den);
+}
+
+__global__ __launch_bounds__(kRowThreads) void grad_batched_kernel(const EnergyArgs *__restrict__ items,
+                                                                   const EnergyTile *__restrict__ rows) {
+    const EnergyTile t = rows[blockIdx.x];
+    const EnergyArgs &a = items[t.item];
+    if (a.grad) grad_rows(a, t.rb * kRowThreads + threadIdx.x);
+}
+
+}  // namespace sci
+
+struct sci_energy_batch_s {
+    int n_items = 0;
+    EnergyArgs *d_items = nullptr;
+    int32_t *d_ncol = nullptr, *d_nblk = nullptr;
+    EnergyTile *d_tiles = nullptr;  // H psi tiles (W=1, W=2), row tiles (W=1, W=2), reduction blocks
+    int64_t n_hpsi[2] = {0, 0}, n_rows[2] = {0, 0}, n_red = 0;
+    char *d_ws = nullptr;
+};
+
+extern "C" int32_t sci_energy_batch_destroy(sci_energy_batch_t b) {
+    if (!b) return SCI_OK;
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_ncol) (void)hipFree(b->d_ncol);
+    if (b->d_nblk) (void)hipFree(b->d_nblk);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    delete b;
+    return SCI_OK;
+}
+
+extern "C" int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t n_items, uint32_t *dev_flags,
+                                           sci_energy_batch_t *out) {
+    set_error("");
+    if (!out) return fail(SCI_EINVAL, "sci_energy_batch_create: NULL output handle");
+    *out = nullptr;
+    if (n_items < 1 || !items) return fail(SCI_EINVAL, "sci_energy_batch_create: empty item list");
+    if (!dev_flags) return fail(SCI_EINVAL, "sci_energy_batch_create: dev_flags is NULL");
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    std::vector<EnergyArgs> args((size_t)n_items);
+    std::vector<int32_t> ncol((size_t)n_items), nblk((size_t)n_items);
+    std::vector<size_t> ws_off((size_t)n_items);
+    std::vector<EnergyTile> hp[2], rows[2], red;
+    size_t ws = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const sci_energy_item &it = items[i];
+        if (!it.ham) return fail(SCI_EINVAL, "sci_energy_batch_create: item %d has no handle", i);
+        if (it.n_sel < 1) return fail(SCI_EINVAL, "sci_energy_batch_create: item %d has n_sel < 1", i);
+        if (!it.sel || !it.psi || !it.energy) return fail(SCI_EINVAL, "sci_energy_batch_create: item %d NULL buffer", i);
+        const HamDev &d = it.ham->dev;
+        if (d.W > SCI_MAX_WORDS) return fail(SCI_EUNSUPPORTED, "sci_energy_batch_create: item %d W=%d", i, d.W);
+        ws_off[(size_t)i] = ws;
+        ws += energy_ws(it.n_sel);
+        ncol[(size_t)i] = col_split(it.n_sel);
+        nblk[(size_t)i] = (int32_t)reduce_blocks(it.n_sel);
+        const int w = d.W - 1;
+        const int64_t row_blocks = ceil_div(it.n_sel, kRowThreads);
+        for (int64_t rb = 0; rb < row_blocks; ++rb) {
+            for (int cb = 0; cb < ncol[(size_t)i]; ++cb) hp[w].push_back(EnergyTile{i, cb, rb});
+            rows[w].push_back(EnergyTile{i, 0, rb});
+        }
+        for (int64_t k = 0; k < nblk[(size_t)i]; ++k) red.push_back(EnergyTile{i, 0, k});
+    }
+    std::vector<EnergyTile> tiles;
+    for (int w = 0; w < 2; ++w) tiles.insert(tiles.end(), hp[w].begin(), hp[w].end());
+    for (int w = 0; w < 2; ++w) tiles.insert(tiles.end(), rows[w].begin(), rows[w].end());
+    tiles.insert(tiles.end(), red.begin(), red.end());
+
+    sci_energy_batch_s *b = new sci_energy_batch_s;
+    b->n_items = n_items;
+    b->n_hpsi[0] = (int64_t)hp[0].size();
+    b->n_hpsi[1] = (int64_t)hp[1].size();
+    b->n_rows[0] = (int64_t)rows[0].size();
+    b->n_rows[1] = (int64_t)rows[1].size();
+    b->n_red = (int64_t)red.size();
+    auto bail = [&](int32_t st) {
+        sci_energy_batch_destroy(b);
+        return st;
+    };
+    if (hipMalloc((void **)&b->d_items, args.size() * sizeof(EnergyArgs)) != hipSuccess ||
+        hipMalloc((void **)&b->d_ncol, ncol.size() * 4) != hipSuccess ||
+        hipMalloc((void **)&b->d_nblk, nblk.size() * 4) != hipSuccess ||
+        hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(EnergyTile)) != hipSuccess ||
+        hipMalloc((void **)&b->d_ws, std::max<size_t>(ws, 256)) != hipSuccess)
+        return bail(fail(SCI_ENOMEM, "sci_energy_batch_create: device allocation failed"));
+    for (int32_t i = 0; i < n_items; ++i) {
+        const sci_energy_item &it = items[i];
+        const HamDev &d = it.ham->dev;
+        const int64_t n_sel = it.n_sel;
+        char *w = b->d_ws + ws_off[(size_t)i];
+        EnergyArgs &a = args[(size_t)i];
+        a.n = d.n_orb;
+        a.na = d.n_alpha;
+        a.nb = d.n_beta;
+        a.h1 = d.h1;
+        a.eri = d.eri;
+        a.vdir = d.vdir;
+        a.vanti = d.vanti;
+        a.jmat = d.jmat;
+        a.kmat = d.kmat;
+        a.sel = it.sel;
+        a.n_sel = n_sel;
+        a.psi = it.psi;
+        a.hpsi = it.h_psi ? it.h_psi : (double *)w;
+        a.partial = (double *)(w + al((size_t)n_sel * 8));
+        a.scalars = (double *)(w + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16));
+        a.partial_rows = (double *)(w + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16));
+        a.energy = it.energy;
+        a.grad = it.grad;
+        a.flags = dev_flags;
+    }
+    if (hipMemcpy(b->d_items, args.data(), args.size() * sizeof(EnergyArgs), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_ncol, ncol.data(), ncol.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_nblk, nblk.data(), nblk.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(EnergyTile), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(SCI_EHIP, "sci_energy_batch_create: upload failed"));
+    *out = b;
+    return SCI_OK;
+}
+
+extern "C" int32_t sci_energy_batched(sci_energy_batch_t b, sci_stream_t stream) {
+    set_error("");
+    if (!b) return fail(SCI_EINVAL, "sci_energy_batched: NULL handle");
+    hipStream_t st = (hipStream_t)stream;
+    const EnergyArgs *it = b->d_items;
+    const EnergyTile *hp1 = b->d_tiles, *hp2 = hp1 + b->n_hpsi[0];
+    const EnergyTile *r1 = hp2 + b->n_hpsi[1], *r2 = r1 + b->n_rows[0], *red = r2 + b->n_rows[1];
+    if (b->n_hpsi[0]) SCI_LAUNCH(hpsi_batched_kernel<1>, dim3((unsigned)b->n_hpsi[0]), dim3(kRowThreads), 0, st, it, b->d_ncol, hp1);
+    if (b->n_hpsi[1]) SCI_LAUNCH(hpsi_batched_kernel<2>, dim3((unsigned)b->n_hpsi[1]), dim3(kRowThreads), 0, st, it, b->d_ncol, hp2);
+    if (b->n_rows[0]) SCI_LAUNCH(hpsi_finish_batched_kernel<1>, dim3((unsigned)b->n_rows[0]), dim3(kRowThreads), 0, st, it, b->d_ncol, r1);
+    if (b->n_rows[1]) SCI_LAUNCH(hpsi_finish_batched_kernel<2>, dim3((unsigned)b->n_rows[1]), dim3(kRowThreads), 0, st, it, b->d_ncol, r2);
+    SCI_LAUNCH(reduce_partial_batched_kernel, dim3((unsigned)b->n_red), dim3(kRedThreads), 0, st, it, red);
+    SCI_LAUNCH(reduce_final_batched_kernel, dim3((unsigned)b->n_items), dim3(kRedThreads), 0, st, it, b->d_nblk);
+    const int64_t nr = b->n_rows[0] + b->n_rows[1];
+    SCI_LAUNCH(grad_batched_kernel, dim3((unsigned)nr), dim3(kRowThreads), 0, st, it, r1);
+    SCI_HIP_TRY(hipGetLastError());
     return SCI_OK;
 }

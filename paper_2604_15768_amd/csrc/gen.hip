@@ -14,6 +14,9 @@
 // fixed.  Screened mode (eps >= 0) keeps |H| > eps and compacts with a wave
 // ballot and one atomic per wave iteration (the paper compacts per block with
 // one atomicAdd per block).
+#include <algorithm>
+#include <vector>
+
 #include "sci_internal.hpp"
 
 namespace sci {
@@ -24,6 +27,7 @@ constexpr int kUnroll = 4;  // row positions per lane per loop trip (loads issue
 
 struct GenArgs {
     // system
+    int W;
     int n, na, nb, va, vb;
     int c1, c2, c3, c4, nc;
     const double *h1, *eri, *vdir, *vanti;
@@ -112,11 +116,9 @@ __device__ __forceinline__ void emit(const GenArgs &a, int64_t o_dense, bool val
 // quantity (row key, integral row base, per-particle sign bits gathered with a
 // ballot) is wave-uniform and lanes walk the particle index without division.
 template <int W, bool DENSE>
-__global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
-    __shared__ GenLds L;
+__device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, GenLds &L) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
-    const int64_t src = a.src_first + blockIdx.x;
     const int64_t flat0 = src * a.nc;
     const int64_t lo = (a.exc_begin > flat0 ? a.exc_begin : flat0) - flat0;
     const int64_t hi = (a.exc_end < flat0 + a.nc ? a.exc_end : flat0 + a.nc) - flat0;
@@ -363,6 +365,83 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
     }
 }
 
+template <int W, bool DENSE>
+__global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
+    __shared__ GenLds L;
+    gen_source<W, DENSE>(a, a.src_first + blockIdx.x, L);
+}
+
+// A tile: n_src consecutive sources of one system of a batch.
+struct GenTile {
+    int32_t item;
+    int32_t n_src;
+    int64_t src0;
+};
+
+// Many systems of one key width in one launch: a persistent grid takes tiles
+// from a device counter (tiles are ordered largest first); each tile's system
+// arguments come from the batch's device table through scalar loads.
+template <int W>
+__global__ __launch_bounds__(kGenThreads) void gen_batched_kernel(const GenArgs *__restrict__ items,
+                                                                  const GenTile *__restrict__ tiles, int64_t n_tiles,
+                                                                  unsigned long long *next) {
+    __shared__ GenLds L;
+    __shared__ long long s_t;
+    while (true) {
+        __syncthreads();  // the previous source is done with LDS and s_t
+        if (threadIdx.x == 0) s_t = (long long)atomicAdd(next, 1ull);
+        __syncthreads();
+        // the tile index is the same in every lane: say so, so the tile and its system's
+        // arguments are read with scalar loads
+        const uint64_t tu = (uint64_t)s_t;
+        const int64_t t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tu >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tu));
+        if (t >= n_tiles) break;
+        const GenTile tile = tiles[t];
+        const GenArgs &a = items[tile.item];
+        for (int j = 0; j < tile.n_src; ++j) {
+            if (j > 0) __syncthreads();
+            gen_source<W, true>(a, tile.src0 + j, L);
+        }
+    }
+}
+
+static GenArgs make_gen_args(const HamDev &d, const uint64_t *dets, int64_t exc_begin, int64_t exc_end,
+                             uint64_t *out_keys, double *out_hij, int32_t *out_src, int64_t capacity,
+                             unsigned long long *n_out, uint32_t *dev_flags, double eps) {
+    GenArgs a;
+    a.W = d.W;
+    a.n = d.n_orb;
+    a.na = d.n_alpha;
+    a.nb = d.n_beta;
+    a.va = d.v_alpha;
+    a.vb = d.v_beta;
+    a.c1 = (int)d.c1;
+    a.c2 = (int)d.c2;
+    a.c3 = (int)d.c3;
+    a.c4 = (int)d.c4;
+    a.nc = (int)d.n_coupled;
+    a.h1 = d.h1;
+    a.eri = d.eri;
+    a.vdir = d.vdir;
+    a.vanti = d.vanti;
+    for (int t = 0; t < 4; ++t) a.pairs[t] = d.pairs[t];
+    a.dets = dets;
+    a.src_first = exc_begin / d.n_coupled;
+    a.pva = (int)comb2(d.v_alpha);
+    a.pvb = (int)comb2(d.v_beta);
+    a.exc_begin = exc_begin;
+    a.exc_end = exc_end;
+    a.keys = out_keys;
+    a.hij = out_hij;
+    a.src_out = out_src;
+    a.capacity = capacity;
+    a.n_out = n_out;
+    a.flags = dev_flags;
+    a.eps = eps;
+    return a;
+}
+
 }  // namespace sci
 
 using namespace sci;
@@ -397,38 +476,9 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
     if (exc_end == exc_begin) return SCI_OK;
     if (!dets || !out_keys || !out_hij) return fail(SCI_EINVAL, "sci_gen_coupled: NULL buffer");
 
-    GenArgs a;
-    a.n = d.n_orb;
-    a.na = d.n_alpha;
-    a.nb = d.n_beta;
-    a.va = d.v_alpha;
-    a.vb = d.v_beta;
-    a.c1 = (int)d.c1;
-    a.c2 = (int)d.c2;
-    a.c3 = (int)d.c3;
-    a.c4 = (int)d.c4;
-    a.nc = (int)d.n_coupled;
-    a.h1 = d.h1;
-    a.eri = d.eri;
-    a.vdir = d.vdir;
-    a.vanti = d.vanti;
-    for (int t = 0; t < 4; ++t) a.pairs[t] = d.pairs[t];
-    a.dets = dets;
-    a.src_first = exc_begin / d.n_coupled;
-    const int64_t src_last = (exc_end - 1) / d.n_coupled;
-    const int64_t n_src = src_last - a.src_first + 1;
-    a.pva = (int)comb2(d.v_alpha);
-    a.pvb = (int)comb2(d.v_beta);
-    a.exc_begin = exc_begin;
-    a.exc_end = exc_end;
-    a.keys = out_keys;
-    a.hij = out_hij;
-    a.src_out = out_src;
-    a.capacity = capacity;
-    a.n_out = (unsigned long long *)n_out;
-    a.flags = dev_flags;
-    a.eps = eps;
-
+    GenArgs a = make_gen_args(d, dets, exc_begin, exc_end, out_keys, out_hij, out_src, capacity,
+                              (unsigned long long *)n_out, dev_flags, eps);
+    const int64_t n_src = (exc_end - 1) / d.n_coupled - a.src_first + 1;
     const int64_t grid = n_src;
     if (grid > 0x7fffffffll) return fail(SCI_EUNSUPPORTED, "sci_gen_coupled: range too large for one launch");
     dim3 g((unsigned)grid), b(kGenThreads);
@@ -440,5 +490,181 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
         else SCI_LAUNCH((gen_kernel<2, false>), g, b, 0, st, a);
     }
     SCI_HIP_TRY(hipGetLastError());
+    return SCI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of systems (one persistent launch)
+// ---------------------------------------------------------------------------
+
+struct sci_gen_batch_s {
+    std::vector<GenArgs> items;
+    GenArgs *d_items = nullptr;
+    GenTile *d_tiles = nullptr;        // W=1 tiles, then W=2 tiles
+    unsigned long long *d_next = nullptr;  // one work counter per key width
+    int64_t n_tiles[2] = {0, 0}, tile_alloc = 0;
+    int64_t tile_candidates = 0;
+    int grid[2] = {0, 0};
+};
+
+namespace sci {
+
+// tiles of about tile_cand candidates (at least one source) of the systems of key
+// width W, largest first
+static void build_tiles(const std::vector<GenArgs> &items, int W, int64_t tile_cand, std::vector<GenTile> &tiles) {
+    tiles.clear();
+    for (size_t i = 0; i < items.size(); ++i) {
+        const GenArgs &a = items[i];
+        if (a.W != W || a.exc_end <= a.exc_begin) continue;
+        const int64_t s0 = a.src_first, s1 = (a.exc_end - 1) / a.nc;
+        const int64_t per = std::min<int64_t>(std::max<int64_t>(1, tile_cand / a.nc), 1 << 20);
+        for (int64_t src = s0; src <= s1; src += per)
+            tiles.push_back(GenTile{(int32_t)i, (int32_t)std::min<int64_t>(per, s1 - src + 1), src});
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const GenTile &x, const GenTile &y) {
+        return (int64_t)x.n_src * items[x.item].nc > (int64_t)y.n_src * items[y.item].nc;
+    });
+}
+
+static int32_t upload_tiles(sci_gen_batch_s *b, int64_t tile_cand) {
+    std::vector<GenTile> tiles, t2;
+    build_tiles(b->items, 1, tile_cand, tiles);
+    build_tiles(b->items, 2, tile_cand, t2);
+    b->n_tiles[0] = (int64_t)tiles.size();
+    b->n_tiles[1] = (int64_t)t2.size();
+    tiles.insert(tiles.end(), t2.begin(), t2.end());
+    const int64_t nt = (int64_t)tiles.size();
+    if (nt > b->tile_alloc) {
+        if (b->d_tiles) (void)hipFree(b->d_tiles);
+        b->d_tiles = nullptr;
+        SCI_HIP_TRY(hipMalloc((void **)&b->d_tiles, (size_t)std::max<int64_t>(nt, 1) * sizeof(GenTile)));
+        b->tile_alloc = std::max<int64_t>(nt, 1);
+    }
+    if (nt) SCI_HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), (size_t)nt * sizeof(GenTile), hipMemcpyHostToDevice));
+    b->tile_candidates = tile_cand;
+    return SCI_OK;
+}
+
+static int32_t launch_batch(sci_gen_batch_s *b, hipStream_t st) {
+    if (b->n_tiles[0] > 0) {
+        SCI_HIP_TRY(launch_set_i64((int64_t *)b->d_next, 0, st));
+        SCI_LAUNCH(gen_batched_kernel<1>, dim3((unsigned)b->grid[0]), dim3(kGenThreads), 0, st,
+                   (const GenArgs *)b->d_items, (const GenTile *)b->d_tiles, b->n_tiles[0], b->d_next);
+    }
+    if (b->n_tiles[1] > 0) {
+        SCI_HIP_TRY(launch_set_i64((int64_t *)(b->d_next + 1), 0, st));
+        SCI_LAUNCH(gen_batched_kernel<2>, dim3((unsigned)b->grid[1]), dim3(kGenThreads), 0, st,
+                   (const GenArgs *)b->d_items, (const GenTile *)(b->d_tiles + b->n_tiles[0]), b->n_tiles[1],
+                   b->d_next + 1);
+    }
+    SCI_HIP_TRY(hipGetLastError());
+    return SCI_OK;
+}
+
+}  // namespace sci
+
+extern "C" int32_t sci_gen_batch_destroy(sci_gen_batch_t b) {
+    if (!b) return SCI_OK;
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_next) (void)hipFree(b->d_next);
+    delete b;
+    return SCI_OK;
+}
+
+extern "C" int32_t sci_gen_batch_create(const sci_gen_item *items, int32_t n_items, int64_t tile_candidates,
+                                        uint32_t *dev_flags, sci_gen_batch_t *out) {
+    set_error("");
+    if (!out) return fail(SCI_EINVAL, "sci_gen_batch_create: NULL output handle");
+    *out = nullptr;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(SCI_EINVAL, "sci_gen_batch_create: bad item list");
+    if (tile_candidates < 1) return fail(SCI_EINVAL, "sci_gen_batch_create: tile_candidates must be >= 1");
+    if (!dev_flags) return fail(SCI_EINVAL, "sci_gen_batch_create: dev_flags is NULL");
+    std::vector<GenArgs> args;
+    args.reserve((size_t)n_items);
+    for (int32_t i = 0; i < n_items; ++i) {
+        const sci_gen_item &it = items[i];
+        if (!it.ham) return fail(SCI_EINVAL, "sci_gen_batch_create: item %d has no handle", i);
+        const HamDev &d = it.ham->dev;
+        const int64_t total = it.n_dets * d.n_coupled;
+        if (it.n_dets < 0 || it.exc_begin < 0 || it.exc_end < it.exc_begin || it.exc_end > total)
+            return fail(SCI_EINVAL, "sci_gen_batch_create: item %d range [%lld,%lld) outside [0,%lld)", i,
+                        (long long)it.exc_begin, (long long)it.exc_end, (long long)total);
+        if (d.W > SCI_MAX_WORDS || d.n_coupled >= (1ll << 24))
+            return fail(SCI_EUNSUPPORTED, "sci_gen_batch_create: item %d exceeds the kernel's limits", i);
+        if (it.exc_end > it.exc_begin && (!it.dets || !it.out_keys || !it.out_hij))
+            return fail(SCI_EINVAL, "sci_gen_batch_create: item %d has a NULL buffer", i);
+        args.push_back(make_gen_args(d, it.dets, it.exc_begin, it.exc_end, it.out_keys, it.out_hij, nullptr,
+                                     it.exc_end - it.exc_begin, nullptr, dev_flags, -1.0));
+    }
+    sci_gen_batch_s *b = new sci_gen_batch_s;
+    b->items = std::move(args);
+    auto bail = [&](int32_t st) {
+        sci_gen_batch_destroy(b);
+        return st;
+    };
+    if (hipMalloc((void **)&b->d_items, std::max<size_t>(b->items.size(), 1) * sizeof(GenArgs)) != hipSuccess ||
+        hipMalloc((void **)&b->d_next, 256) != hipSuccess)
+        return bail(fail(SCI_ENOMEM, "sci_gen_batch_create: device allocation failed"));
+    if (!b->items.empty() &&
+        hipMemcpy(b->d_items, b->items.data(), b->items.size() * sizeof(GenArgs), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(SCI_EHIP, "sci_gen_batch_create: upload failed"));
+    const int32_t st = upload_tiles(b, tile_candidates);
+    if (st != SCI_OK) return bail(st);
+    int dev = 0, n_cu = 256, per1 = 1, per2 = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, gen_batched_kernel<1>, kGenThreads, 0) != hipSuccess ||
+        per1 < 1)
+        per1 = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, gen_batched_kernel<2>, kGenThreads, 0) != hipSuccess ||
+        per2 < 1)
+        per2 = 1;
+    b->grid[0] = std::max(1, n_cu) * per1;
+    b->grid[1] = std::max(1, n_cu) * per2;
+    *out = b;
+    return SCI_OK;
+}
+
+extern "C" int32_t sci_gen_coupled_batched(sci_gen_batch_t batch, sci_stream_t stream) {
+    set_error("");
+    if (!batch) return fail(SCI_EINVAL, "sci_gen_coupled_batched: NULL handle");
+    return launch_batch(batch, (hipStream_t)stream);
+}
+
+extern "C" int32_t sci_gen_batch_autotune(sci_gen_batch_t batch, sci_stream_t stream, int64_t *tile_candidates) {
+    set_error("");
+    if (!batch) return fail(SCI_EINVAL, "sci_gen_batch_autotune: NULL handle");
+    hipStream_t st = (hipStream_t)stream;
+    static const int64_t kTry[] = {1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SCI_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SCI_EHIP, "sci_gen_batch_autotune: event creation failed");
+    }
+    int64_t best = batch->tile_candidates;
+    float best_ms = -1.0f;
+    int32_t rc = SCI_OK;
+    for (int64_t tc : kTry) {
+        if ((rc = upload_tiles(batch, tc)) != SCI_OK) break;
+        if ((rc = launch_batch(batch, st)) != SCI_OK) break;  // warm
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SCI_EHIP, "sci_gen_batch_autotune: event"); break; }
+        if ((rc = launch_batch(batch, st)) != SCI_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(SCI_EHIP, "sci_gen_batch_autotune: event");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = tc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SCI_OK) return rc;
+    if ((rc = upload_tiles(batch, best)) != SCI_OK) return rc;
+    if (tile_candidates) *tile_candidates = best;
     return SCI_OK;
 }

@@ -259,6 +259,9 @@ def select_levels(rng, n_orb, n_alpha, n_beta, n_sel, max_level=4) -> np.ndarray
     total = pops.sum()
     if n_sel - 1 > total:
         raise ValueError("not enough determinants up to the requested level")
+    if n_sel - 1 > 0.25 * total and math.comb(n_orb, n_alpha) * math.comb(n_orb, n_beta) <= 4_000_000:
+        # a large share of a small space: enumerate it and take a uniform subset
+        return _select_levels_enumerated(rng, n_orb, n_alpha, n_beta, n_sel, max_level)
     ref_bits = np.zeros(2 * n_orb, dtype=bool)
     ref_bits[:n_alpha] = True
     ref_bits[n_orb:n_orb + n_beta] = True
@@ -287,6 +290,24 @@ def select_levels(rng, n_orb, n_alpha, n_beta, n_sel, max_level=4) -> np.ndarray
         allk = np.concatenate([chosen, _pack_bits(batch, W)])
         keep = _unique_rows_first(allk)
         chosen = allk[keep][: n_sel]
+    return sort_keys(chosen)
+
+
+def _select_levels_enumerated(rng, n_orb, n_alpha, n_beta, n_sel, max_level):
+    full = all_determinants(n_orb, n_alpha, n_beta)
+    W = n_words(n_orb)
+    ref = np.zeros(2 * n_orb, dtype=bool)
+    ref[:n_alpha] = True
+    ref[n_orb:n_orb + n_beta] = True
+    ref_w = _pack_bits(ref[None, :], W)[0]
+    x = full ^ ref_w
+    moved = np.zeros(full.shape[0], dtype=np.int64)
+    for j in range(W):
+        moved += np.unpackbits(x[:, j:j + 1].view(np.uint8), axis=1).sum(axis=1)
+    level = moved // 2
+    pool = np.flatnonzero((level >= 1) & (level <= max_level))
+    pick = rng.choice(pool.shape[0], size=n_sel - 1, replace=False)
+    chosen = np.concatenate([ref_w[None, :], full[pool[np.sort(pick)]]])
     return sort_keys(chosen)
 
 
@@ -394,6 +415,28 @@ def make_system(wl: Workload) -> System:
     psi = prng.standard_normal(dets.shape[0])
     psi /= np.linalg.norm(psi)
     return System(wl, h1, eri, dets, psi)
+
+
+BATCH_SEED = SEED_BASE + 3
+
+
+def batch_workloads(n_sys: int = 64, seed: int = BATCH_SEED):
+    """The batched workload: n_sys systems of uneven size.  Shapes come from one
+    stream seeded with `seed`: n_orb ~ U{10..40}, f ~ U[0.4, 0.6],
+    n_alpha = n_beta = round(f * n_orb), Cholesky rank 4 n_orb, and
+    n_sel = round(exp(U[ln 1e3, ln 5e4])) capped at the reference plus every
+    determinant of excitation level 1-4; system k's integrals and selected set
+    (reference + uniform levels 1-4, as the medium workload) use seed + 1000 (k + 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n_sys):
+        n = int(rng.integers(10, 41))
+        f = float(rng.uniform(0.4, 0.6))
+        ne = int(math.floor(f * n + 0.5))
+        n_sel = int(math.floor(math.exp(rng.uniform(math.log(1e3), math.log(5e4))) + 0.5))
+        avail = 1 + sum(p for _, _, p in _level_populations(n, ne, ne, 4))
+        out.append(Workload(f"batch{k}", n, ne, ne, 4 * n, min(n_sel, avail), "levels", seed + 1000 * (k + 1)))
+    return out
 
 
 def small_workload(n_orb, n_alpha, n_beta, n_sel=None, seed=SEED_BASE + 77, rank=None, selection=None):
