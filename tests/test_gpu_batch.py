@@ -162,3 +162,61 @@ def test_batched_energy_matches_plain_and_oracle():
         assert np.max(np.abs(batch.grad[k].cpu().numpy() - og)) <= G_TOL
     assert checked >= 3
     batch.close()
+
+
+def test_streaming_chunk_loop_graph_replays():
+    """The pool-streaming loop (generation of chunk k+1 on one stream, dedup of chunk k
+    on a second) captured once and replayed: every replay equals the eager result."""
+    from tests.gpu_common import ham
+    sci = require_gpu()
+    s = system("medium")
+    h = ham("medium")
+    dets = s.dets[pick_sources(s.dets.shape[0], 12, 5)]
+    d = sci.keys_to_device(dets)
+    sel = sci.keys_to_device(s.dets)
+    n = dets.shape[0]
+    total = n * h.n_coupled
+    chunk = 70_000
+    cap = total + s.dets.shape[0]
+    dev = torch.device("cuda")
+    set_a = torch.empty((cap, 1), dtype=torch.int64, device=dev)
+    set_b = torch.empty_like(set_a)
+    n_in = torch.tensor([s.dets.shape[0]], dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(sci.sci_stream_workspace_bytes(h, chunk), dtype=torch.uint8, device=dev)
+    flags = sci.new_flags(dev)
+    dd = torch.cuda.Stream()
+
+    def run():
+        cur = torch.cuda.current_stream()
+        is_b = sci.sci_stream_dedup(h, d, n, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out, ws, ws.numel(),
+                                    flags, cur, dd)
+        cur.wait_stream(dd)
+        return is_b
+
+    say(f"captured streaming loop: {total} candidates in chunks of {chunk}")
+    is_b = run()
+    torch.cuda.synchronize()
+    m = int(n_out.item())
+    ref = (set_b if is_b else set_a)[:m].clone()
+    ok, _, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
+    ou, _ = oracle.dedup_merge(1, ok, s.dets)
+    assert m == ou.shape[0] and np.array_equal(sci.keys_to_host(ref), ou)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            is_b2 = run()
+    torch.cuda.synchronize()
+    assert is_b2 == is_b
+    for rep in range(3):
+        set_a.fill_(0)
+        set_b.fill_(0)
+        n_out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(n_out.item()) == m, f"replay {rep}: count"
+        assert torch.equal((set_b if is_b else set_a)[:m], ref), f"replay {rep}: keys"
+    assert sci.check_flags(flags, "captured stream") == 0
