@@ -72,12 +72,18 @@ __device__ int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *s_wav
 
 template <int W>
 __device__ __forceinline__ uint32_t digit_of(const Key<W> &k, int shift) {
-    // 8-bit digits never straddle a word; the word is selected with static indices
-    uint64_t v = k.w[0];
+    // the 8 bits from `shift` up, which may straddle two words; words are selected
+    // with static indices (a runtime index would put the key in scratch)
+    const int q = shift >> 6, r = shift & 63;
+    uint64_t lo = k.w[0], hi = 0;
 #pragma unroll
-    for (int j = 1; j < W; ++j)
-        if ((shift >> 6) == j) v = k.w[j];
-    return (uint32_t)(v >> (shift & 63)) & 0xffu;
+    for (int j = 1; j < W; ++j) {
+        if (q == j) lo = k.w[j];
+        if (q + 1 == j) hi = k.w[j];
+    }
+    uint64_t v = lo >> r;
+    if (r > 56) v |= hi << (64 - r);
+    return (uint32_t)v & 0xffu;
 }
 
 // number of low bits in which keys may differ, given the OR of (key ^ key0)
@@ -85,6 +91,14 @@ template <int W>
 __device__ __forceinline__ int varying_bits(const uint64_t *orx) {
     for (int j = W - 1; j >= 0; --j)
         if (orx[j]) return 64 * j + 64 - __clzll((long long)orx[j]);
+    return 0;
+}
+
+// position of the lowest bit that varies (0 when none does)
+template <int W>
+__device__ __forceinline__ int lowest_varying_bit(const uint64_t *orx) {
+    for (int j = 0; j < W; ++j)
+        if (orx[j]) return 64 * j + __ffsll((unsigned long long)orx[j]) - 1;
     return 0;
 }
 
@@ -836,7 +850,6 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
     __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
     __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
-    __shared__ uint16_t s_rank[C::CAP];      // per-key rank within its wave and digit
     __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];  // per-wave digit counts, then output offsets
     __shared__ uint64_t s_or[2];
     __shared__ int s_u[kBWaves];
@@ -939,6 +952,10 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
 #pragma unroll
         for (int j = 0; j < W; ++j) orx[j] = s_or[j];
         const int nbits = varying_bits<W>(orx);
+        const int lo_bit = lowest_varying_bit<W>(orx);
+        Key<W> orkey;
+#pragma unroll
+        for (int j = 0; j < W; ++j) orkey.w[j] = orx[j];
         int u = 0;
 #pragma unroll
         for (int ww = 0; ww < kBWaves; ++ww) u += s_u[ww];
@@ -950,21 +967,30 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
         const int Kd = (u + kBThreads - 1) / kBThreads;
         const int CHd = Kd * kWave;
         bool first = true;
-        for (int shift = 0; shift < nbits; shift += 8) {
+        // digits cover only the bits that vary in this unit; a window in which no key
+        // differs would be an identity pass and is skipped
+        for (int shift = lo_bit; shift < nbits; shift += 8) {
+            if (digit_of<W>(orkey, shift) == 0u) continue;  // workgroup-uniform
             const int base_pos = first ? my0 : w * CHd;
-            const int rounds = first ? Km : Kd;
+            const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's uniques
             const int limit = first ? my0 + uw : u;
-            for (int d = lane; d < 256; d += kWave) s_cnt[w][d] = 0;
-            for (int k = 0; k < rounds; ++k) {
+            *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = 0ull;
+            // keys and their ranks stay in registers until the scatter below
+            Key<W> kr[kBK];
+            uint32_t rr[kBK];
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                if (k >= rounds) break;  // wave-uniform
                 const int pos = base_pos + k * kWave + lane;
                 const bool valid = pos < limit;
-                const uint32_t d = valid ? digit_of<W>(cur[pos], shift) : 0u;
+                if (valid) kr[k] = cur[pos];
+                const uint32_t d = valid ? digit_of<W>(kr[k], shift) : 0u;
                 int rk;
                 const int tot = wave_match_rank_skip(d, valid, &rk);
                 uint32_t base = 0;
                 if (valid) base = s_cnt[w][d];
                 if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
-                if (valid) s_rank[pos] = (uint16_t)(base + (uint32_t)rk);
+                rr[k] = base + (uint32_t)rk;
             }
             __syncthreads();
             // this wave's output offset per digit: all keys of smaller digits, plus
@@ -989,12 +1015,11 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
                 for (int j = 0; j < 4; ++j) o4 |= (uint64_t)((pre[j] + low[j]) & 0xffffu) << (16 * j);
                 *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = o4;
             }
-            for (int k = 0; k < rounds; ++k) {
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                if (k >= rounds) break;
                 const int pos = base_pos + k * kWave + lane;
-                if (pos < limit) {
-                    const Key<W> key = cur[pos];
-                    nxt[s_cnt[w][digit_of<W>(key, shift)] + s_rank[pos]] = key;
-                }
+                if (pos < limit) nxt[s_cnt[w][digit_of<W>(kr[k], shift)] + rr[k]] = kr[k];
             }
             __syncthreads();
             Key<W> *t = cur;
