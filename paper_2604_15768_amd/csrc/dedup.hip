@@ -500,41 +500,42 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
 // Scatter pass: each key to its bucket's range (order inside a bucket is free).
 template <int W, int FMAX>
 __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
-    // each bucket's output base for this tile, and a 32-bit cursor (a tile holds < 2^32 keys)
-    __shared__ int64_t s_base[FMAX];
-    __shared__ uint32_t s_off[FMAX];
-    const int64_t g = blockIdx.x;
-    if (g >= a.tile_base[a.S_in]) return;
-    const int s = find_segment(a.tile_base, a.S_in, g);
-    const int64_t t = g - a.tile_base[s];
-    const int64_t T = a.tile_base[s + 1] - a.tile_base[s];
-    const int f = a.fan[s];
-    const int64_t start = a.seg_in[s] + t * a.tile;
-    const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
-    const int64_t *cp = a.counts + a.cbase[s];
-    for (int j = threadIdx.x; j < f; j += kDThreads) {
-        s_base[j] = cp[(int64_t)j * T + t];
-        s_off[j] = 0u;
-    }
-    __syncthreads();
-    constexpr int U = 8;
-    for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kDThreads) {
-        Key<W> k[U];
-        int b[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * kDThreads + threadIdx.x;
-            b[u] = -1;
-            if (i < end) {
-                b[u] = a.ids[i];
-                k[u] = load_key<W>(a.in, i);
+    // each bucket's output cursor for this tile: positions are below n < 2^32 (the entry
+    // point refuses larger inputs), so 32 bits hold them and the LDS stays small
+    __shared__ uint32_t s_cur[FMAX];
+    // a small persistent grid walks the tiles: every workgroup keeps one open output
+    // run per bucket, and fewer runs in flight at once merge better in the caches
+    const int64_t n_tiles = a.tile_base[a.S_in];
+    for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+        __syncthreads();  // the previous tile's cursors are no longer read
+        const int s = find_segment(a.tile_base, a.S_in, g);
+        const int64_t t = g - a.tile_base[s];
+        const int64_t T = a.tile_base[s + 1] - a.tile_base[s];
+        const int f = a.fan[s];
+        const int64_t start = a.seg_in[s] + t * a.tile;
+        const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
+        const int64_t *cp = a.counts + a.cbase[s];
+        for (int j = threadIdx.x; j < f; j += kDThreads) s_cur[j] = (uint32_t)cp[(int64_t)j * T + t];
+        __syncthreads();
+        constexpr int U = 8;
+        for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kDThreads) {
+            Key<W> k[U];
+            int b[U];
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + u * kDThreads + threadIdx.x;
+                b[u] = -1;
+                if (i < end) {
+                    b[u] = a.ids[i];
+                    k[u] = load_key<W>(a.in, i);
+                }
             }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (b[u] >= 0) {
-                const uint32_t o = atomicAdd(&s_off[b[u]], 1u);
-                store_key<W>(a.out, s_base[b[u]] + (int64_t)o, k[u]);
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b[u] >= 0) {
+                    const uint32_t pos = atomicAdd(&s_cur[b[u]], 1u);
+                    store_key<W>(a.out, (int64_t)pos, k[u]);
+                }
             }
         }
     }
@@ -1385,6 +1386,9 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     int64_t *sums = (int64_t *)(ws + L.sums);
     // [0] union total, [1] novel total, [2] level counters, [3] oversized units, [4] units, [5] units + 1
     int64_t *scal = (int64_t *)(ws + L.scal);
+    int dev = 0, n_cu_i = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu_i, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t n_cu = std::max(n_cu_i, 1);
     const bool have_set = set_in && n_set_in;
 
     if (have_set && check_set)
@@ -1469,9 +1473,11 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             const int64_t cbound = tiles_bound * (int64_t)a.F;
             SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 2, st));
             if (lvl == 0) {
-                SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
+                           dim3(kDThreads), 0, st, a);
             } else {
-                SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
+                           dim3(kDThreads), 0, st, a);
             }
             const int64_t slots = (int64_t)S_cur * a.F;
             SCI_LAUNCH(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
