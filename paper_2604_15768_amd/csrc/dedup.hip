@@ -2,10 +2,10 @@
 // set.
 //
 // The paper's three steps map onto one device as follows:
-//   step 1 (local sort + regular sampling)  -> regular-stride samples of the
-//          candidates, sorted in LDS (or by one workgroup over global memory
-//          when there are more samples than fit), give splitters at equal
-//          sample ranks;
+//   step 1 (local sort + regular sampling)  -> one sample per equal stratum of
+//          the candidates (hashed offset inside the stratum), sorted in LDS (or
+//          by one workgroup over global memory when there are more samples
+//          than fit), gives splitters at equal sample ranks;
 //   step 2 (splitters + binary search)       -> every key finds its bucket by
 //          binary search over the splitters held in LDS;
 //   step 3 (all-to-all + local merge/unique) -> a histogram/scan/scatter pass
@@ -20,8 +20,9 @@
 //
 // Sort vs. hash (paper section 4.1.2): no hash table and no global atomics on
 // keys; the only atomics are LDS counters.  A bucket larger than the LDS
-// capacity (skewed or heavily repeated keys) is sorted by its workgroup with
-// the same radix ranking over global memory, so every size is handled.
+// capacity (heavily repeated keys) streams through LDS against one hash table
+// when its distinct keys fit, else is sorted by its workgroup with the same
+// radix ranking over global memory, so every size is handled.
 #include <algorithm>
 
 #include "sci_internal.hpp"
@@ -331,8 +332,24 @@ struct LevelArgs {
 
 __device__ __forceinline__ int64_t seg_size(const int64_t *seg, int s) { return seg[s + 1] - seg[s]; }
 
-// One workgroup per input segment: choose the fan-out, draw regular-stride
-// samples, sort them, pick splitters at equal sample ranks.
+// Position of sample k of M from the segment [start, start + size): one sample in
+// each of M equal strata, at a hashed offset inside it (SplitMix64 finaliser of k).
+// A fixed offset would make the sample stride a fixed number of keys, and the
+// generated candidates are laid out with periods (excitations per source, blocks
+// of single excitations) that such a stride can keep hitting at the same phase:
+// whole classes of keys then go unsampled and their buckets grow far past the
+// target.  Hashed offsets keep the stratification and break that resonance.
+__device__ __forceinline__ int64_t sample_pos(int64_t start, int64_t size, int64_t k, int64_t M) {
+    uint64_t x = (uint64_t)k + 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    const int64_t r = (int64_t)__umul64hi(x, (uint64_t)size);  // uniform in [0, size)
+    return start + (k * size + r) / M;                         // in stratum k
+}
+
+// One workgroup per input segment: choose the fan-out, draw one sample per
+// stratum, sort them, pick splitters at equal sample ranks.
 template <int W, bool GLOBAL_SAMPLES>
 __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     using C = DCfg<W>;
@@ -351,8 +368,7 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     if (!GLOBAL_SAMPLES) {
         if (M > C::CAP) return;  // cannot happen: the host picks the global variant
         for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
-            const int64_t pos = start + (k * size + size / 2) / M;  // regular stride
-            s_buf[k] = load_key<W>(a.in, pos);
+            s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k, M));
         }
         __syncthreads();
         const Key<W> ref = s_buf[0];
@@ -366,8 +382,7 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     } else {
         uint64_t *X = a.sample_buf, *Y = a.sample_buf + (int64_t)a.max_samples * W;
         for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
-            const int64_t pos = start + (k * size + size / 2) / M;
-            store_key<W>(X, k, load_key<W>(a.in, pos));
+            store_key<W>(X, k, load_key<W>(a.in, sample_pos(start, size, k, M)));
         }
         __threadfence();
         __syncthreads();
@@ -649,6 +664,8 @@ struct BucketArgs {
     int64_t *ncount;          // [n_units + 1] novel size per unit (scanned later)
     int64_t *n_big;           // device count of oversized units (single buckets above CAP)
     int64_t *big;             // [n_units] their unit indices
+    int64_t *n_big2;          // those with more distinct keys than LDS holds
+    int64_t *big2;            // [n_units] their unit indices (sorted over global memory)
 };
 
 __device__ __forceinline__ void unit_span(const BucketArgs &a, int64_t u, int64_t &start, int64_t &size) {
@@ -845,6 +862,101 @@ __device__ __forceinline__ void wave_scan256(const uint32_t tot[4], uint32_t pre
 constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
 
+// One stable LSD pass of the 512-thread unit sort on the 8-bit digit at `shift`.  This
+// wave's keys are cur[base_pos + k*64 + lane] for k < rounds, positions below `limit`;
+// each key goes to nxt at (keys of smaller digits) + (keys of its digit in lower waves
+// or earlier in this wave).  Keys and ranks stay in registers between the two sweeps.
+template <int W, int KB>
+__device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, int shift, int base_pos, int rounds,
+                                                int limit, uint16_t (*s_cnt)[256]) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    constexpr int kBK = KB;
+    *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = 0ull;
+    // keys and their ranks stay in registers until the scatter below
+    Key<W> kr[kBK];
+    uint32_t rr[kBK];
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) {
+        if (k >= rounds) break;  // wave-uniform
+        const int pos = base_pos + k * kWave + lane;
+        const bool valid = pos < limit;
+        if (valid) kr[k] = cur[pos];
+        const uint32_t d = valid ? digit_of<W>(kr[k], shift) : 0u;
+        int rk;
+        const int tot = wave_match_rank_skip(d, valid, &rk);
+        uint32_t base = 0;
+        if (valid) base = s_cnt[w][d];
+        if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
+        rr[k] = base + (uint32_t)rk;
+    }
+    __syncthreads();
+    // this wave's output offset per digit: all keys of smaller digits, plus
+    // keys of this digit held by lower waves (each wave computes its own row)
+    // (each lane holds digits 4*lane .. 4*lane+3: one 8-byte LDS read per wave row)
+    uint32_t tot[4] = {0u, 0u, 0u, 0u}, pre[4], low[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int ww = 0; ww < kBWaves; ++ww) {
+        const uint64_t c4 = *reinterpret_cast<const uint64_t *>(&s_cnt[ww][4 * lane]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t c = (uint32_t)(c4 >> (16 * j)) & 0xffffu;
+            tot[j] += c;
+            low[j] += (ww < w) ? c : 0u;
+        }
+    }
+    wave_scan256(tot, pre);
+    __syncthreads();  // every wave has read the counts before rows are overwritten
+    {
+        uint64_t o4 = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o4 |= (uint64_t)((pre[j] + low[j]) & 0xffffu) << (16 * j);
+        *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = o4;
+    }
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) {
+        if (k >= rounds) break;
+        const int pos = base_pos + k * kWave + lane;
+        if (pos < limit) nxt[s_cnt[w][digit_of<W>(kr[k], shift)] + rr[k]] = kr[k];
+    }
+    __syncthreads();
+}
+
+// The sorted unique run of unit s (cur[0..u) in LDS) to its place in dst, the set
+// keys of its range it shares, and the unit's counts.  A short set range is streamed
+// once and each of its keys searched among the unique keys in LDS; a long one is
+// searched per unique key instead, whichever moves fewer bytes.
+template <int W>
+__device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, const Key<W> *cur, int u, int64_t start,
+                                            int64_t bl, int64_t bh, int64_t *s_wsum) {
+    int64_t hit = 0;
+    const int64_t nb = bh - bl;
+    const bool stream_set = nb > 0 && nb <= 56 * (int64_t)u;
+    for (int i = threadIdx.x; i < u; i += kBThreads) {
+        const Key<W> key = cur[i];
+        store_key<W>(a.dst, start + i, key);
+        if (nb > 0 && !stream_set && contains_set<W>(a.B, bl, bh, key)) ++hit;
+    }
+    if (stream_set) {
+        for (int64_t j = bl + threadIdx.x; j < bh; j += kBThreads) {
+            const Key<W> key = load_key<W>(a.B, j);
+            int lo = 0, hi = u;  // first unique key not below `key`
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_less<W>(cur[mid], key)) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < u && key_eq<W>(cur[lo], key)) ++hit;
+        }
+    }
+    int64_t matches = 0;
+    if (nb > 0) block_excl_scan_i64<kBWaves>(hit, &matches, s_wsum);
+    if (threadIdx.x == 0) {
+        a.nuniq[s] = u;
+        a.ucount[s] = u + nb - matches;
+        a.ncount[s] = u - matches;
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
@@ -862,7 +974,6 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
     unit_span(a, s, start, size);
     const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
 
-    int64_t nu = 0, matches = 0;
     if (size > C::CAP) {
         // sorted by bucket_big_kernel
         if (threadIdx.x == 0) {
@@ -975,54 +1086,7 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
             const int base_pos = first ? my0 : w * CHd;
             const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's uniques
             const int limit = first ? my0 + uw : u;
-            *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = 0ull;
-            // keys and their ranks stay in registers until the scatter below
-            Key<W> kr[kBK];
-            uint32_t rr[kBK];
-#pragma unroll
-            for (int k = 0; k < kBK; ++k) {
-                if (k >= rounds) break;  // wave-uniform
-                const int pos = base_pos + k * kWave + lane;
-                const bool valid = pos < limit;
-                if (valid) kr[k] = cur[pos];
-                const uint32_t d = valid ? digit_of<W>(kr[k], shift) : 0u;
-                int rk;
-                const int tot = wave_match_rank_skip(d, valid, &rk);
-                uint32_t base = 0;
-                if (valid) base = s_cnt[w][d];
-                if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
-                rr[k] = base + (uint32_t)rk;
-            }
-            __syncthreads();
-            // this wave's output offset per digit: all keys of smaller digits, plus
-            // keys of this digit held by lower waves (each wave computes its own row)
-            // (each lane holds digits 4*lane .. 4*lane+3: one 8-byte LDS read per wave row)
-            uint32_t tot[4] = {0u, 0u, 0u, 0u}, pre[4], low[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int ww = 0; ww < kBWaves; ++ww) {
-                const uint64_t c4 = *reinterpret_cast<const uint64_t *>(&s_cnt[ww][4 * lane]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t c = (uint32_t)(c4 >> (16 * j)) & 0xffffu;
-                    tot[j] += c;
-                    low[j] += (ww < w) ? c : 0u;
-                }
-            }
-            wave_scan256(tot, pre);
-            __syncthreads();  // every wave has read the counts before rows are overwritten
-            {
-                uint64_t o4 = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) o4 |= (uint64_t)((pre[j] + low[j]) & 0xffffu) << (16 * j);
-                *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = o4;
-            }
-#pragma unroll
-            for (int k = 0; k < kBK; ++k) {
-                if (k >= rounds) break;
-                const int pos = base_pos + k * kWave + lane;
-                if (pos < limit) nxt[s_cnt[w][digit_of<W>(kr[k], shift)] + rr[k]] = kr[k];
-            }
-            __syncthreads();
+            unit_radix_pass<W, kBK>(cur, nxt, shift, base_pos, rounds, limit, s_cnt);
             Key<W> *t = cur;
             cur = nxt;
             nxt = t;
@@ -1040,24 +1104,153 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
             __syncthreads();
             cur = s_k1;
         }
-        // the sorted unique run to the bucket's offset; set hits for the union count
-        int64_t hit = 0;
-        for (int i = threadIdx.x; i < u; i += kBThreads) {
-            const Key<W> key = cur[i];
-            store_key<W>(a.dst, start + i, key);
-            if (bh > bl && contains_set<W>(a.B, bl, bh, key)) ++hit;
-        }
-        nu = u;
-        if (bh > bl) {
-            int64_t ht;
-            block_excl_scan_i64<kBWaves>(hit, &ht, s_wsum);
-            matches = ht;
-        }
+        finish_unit<W>(a, s, cur, u, start, bl, bh, s_wsum);
+        return;
     }
-    if (threadIdx.x == 0) {
-        a.nuniq[s] = nu;
-        a.ucount[s] = nu + (bh - bl) - matches;
-        a.ncount[s] = nu - matches;
+    if (threadIdx.x == 0) {  // an empty unit: its range holds only set keys
+        a.nuniq[s] = 0;
+        a.ucount[s] = bh - bl;
+        a.ncount[s] = 0;
+    }
+}
+
+// Oversized units, mostly a few keys repeated many times: the keys stream through
+// LDS in CAP-key chunks against one unit-wide hash table, and first occurrences
+// collect in LDS.  When the distinct keys fit they are sorted there as in
+// bucket_kernel; otherwise the unit moves on to bucket_big_kernel.
+template <int W>
+__global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) {
+    using C = DCfg<W>;
+    constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;
+    constexpr int kLogT = __builtin_ctz(4 * C::CAP);  // 4 CAP slots: load at most 1/2
+    constexpr uint32_t kTMask = (4u * C::CAP) - 1u;
+    __shared__ Key<W> s_in[C::CAP];     // the current chunk; radix ping-pong at the end
+    __shared__ Key<W> s_uq[C::CAP];     // distinct keys so far
+    __shared__ uint32_t s_tab[2 * C::CAP];  // 16-bit slots: index < CAP in s_uq, CAP + i in s_in
+    __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];
+    __shared__ uint64_t s_or[2];
+    __shared__ int s_nu, s_over;
+    __shared__ int64_t s_wsum[kBWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t n_big = *a.n_big;
+    for (int64_t t = blockIdx.x; t < n_big; t += gridDim.x) {
+        const int64_t s = a.big[t];
+        int64_t start, size;
+        unit_span(a, s, start, size);
+        const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
+        const Key<W> ref = load_key<W>(a.src, start);
+        for (int i = threadIdx.x; i < 2 * C::CAP; i += kBThreads) s_tab[i] = 0xffffffffu;
+        if (threadIdx.x == 0) {
+            s_nu = 0;
+            s_over = 0;
+            s_or[0] = s_or[1] = 0;
+        }
+        uint64_t acc[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[j] = 0;
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < size; c0 += C::CAP) {
+            const int m = (int)std::min<int64_t>(C::CAP, size - c0);
+            Key<W> kk[kBK];
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                const int i = k * kBThreads + threadIdx.x;
+                if (i < m) kk[k] = load_key<W>(a.src, start + c0 + i);
+            }
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                const int i = k * kBThreads + threadIdx.x;
+                if (i < m) s_in[i] = kk[k];
+            }
+            __syncthreads();
+            uint32_t fresh = 0, slot[kBK];
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                const int i = k * kBThreads + threadIdx.x;
+                if (i >= m) continue;
+                uint32_t h = key_hash<W>(kk[k], kLogT);
+                // At most 2 CAP keys (CAP distinct so far, CAP in this chunk) occupy the 4 CAP
+                // slots, and each failed exchange follows another lane's insertion: the walk
+                // ends within 4 CAP visits plus 2 CAP retries.
+                for (int probe = 0; probe < 8 * C::CAP; ++probe) {
+                    const uint32_t cur = s_tab[h >> 1];
+                    const uint32_t v = (h & 1u) ? (cur >> 16) : (cur & 0xffffu);
+                    if (v == 0xffffu) {
+                        const uint32_t idx = (uint32_t)(C::CAP + i);
+                        const uint32_t want = (h & 1u) ? ((cur & 0xffffu) | (idx << 16)) : ((cur & 0xffff0000u) | idx);
+                        if (atomicCAS(&s_tab[h >> 1], cur, want) == cur) {
+                            fresh |= 1u << k;
+                            slot[k] = h;
+                            break;
+                        }
+                        continue;  // the word changed: look at this slot again
+                    }
+                    const Key<W> other = v < (uint32_t)C::CAP ? s_uq[v] : s_in[v - C::CAP];
+                    if (key_eq<W>(other, kk[k])) break;  // seen before
+                    h = (h + 1u) & kTMask;
+                }
+            }
+            __syncthreads();
+            // this chunk's first occurrences join the distinct keys (one LDS atomic per wave and round)
+#pragma unroll
+            for (int k = 0; k < kBK; ++k) {
+                const bool keep = (fresh >> k) & 1u;
+                const uint64_t bal = __ballot(keep);
+                if (bal == 0ull) continue;
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&s_nu, __popcll(bal));
+                base = __shfl(base, 0);
+                if (keep) {
+                    const int pos = base + __popcll(bal & lanemask_lt());
+                    if (pos < C::CAP) {
+                        s_uq[pos] = kk[k];
+                        // the slot now names s_uq[pos] instead of s_in[i]; the word's other
+                        // slot may change meanwhile, so flip just this slot's bits
+                        const uint32_t h = slot[k];
+                        const uint32_t flip = (uint32_t)(C::CAP + k * kBThreads + threadIdx.x) ^ (uint32_t)pos;
+                        atomicXor(&s_tab[h >> 1], (h & 1u) ? (flip << 16) : flip);
+#pragma unroll
+                        for (int j = 0; j < W; ++j) acc[j] |= kk[k].w[j] ^ ref.w[j];
+                    } else {
+                        s_over = 1;
+                    }
+                }
+            }
+            __syncthreads();
+            if (s_over) break;  // workgroup-uniform after the barrier
+        }
+        if (s_over) {
+            if (threadIdx.x == 0) {
+                const unsigned long long q = atomicAdd((unsigned long long *)a.n_big2, 1ull);
+                a.big2[q] = s;
+            }
+            __syncthreads();
+            continue;
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const uint64_t o = wave_or64(acc[j]);
+            if (lane == 0 && o) atomicOr((unsigned long long *)&s_or[j], (unsigned long long)o);
+        }
+        __syncthreads();
+        uint64_t orx[W];
+        Key<W> orkey;
+#pragma unroll
+        for (int j = 0; j < W; ++j) orkey.w[j] = orx[j] = s_or[j];
+        const int nbits = varying_bits<W>(orx);
+        const int lo_bit = lowest_varying_bit<W>(orx);
+        const int u = s_nu;
+        Key<W> *cur = s_uq, *nxt = s_in;
+        const int Kd = (u + kBThreads - 1) / kBThreads;
+        for (int shift = lo_bit; shift < nbits; shift += 8) {
+            if (digit_of<W>(orkey, shift) == 0u) continue;
+            unit_radix_pass<W, kBK>(cur, nxt, shift, w * Kd * kWave, Kd, u, s_cnt);
+            Key<W> *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+        finish_unit<W>(a, s, cur, u, start, bl, bh, s_wsum);
+        __syncthreads();  // LDS is reused by the next unit
     }
 }
 
@@ -1067,9 +1260,9 @@ __global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
 template <int W>
 __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
     __shared__ BucketLds L;
-    const int64_t n_big = *a.n_big;
+    const int64_t n_big = *a.n_big2;
     for (int64_t t = blockIdx.x; t < n_big; t += gridDim.x) {
-        const int64_t s = a.big[t];
+        const int64_t s = a.big2[t];
         int64_t start, size;
         unit_span(a, s, start, size);
         const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
@@ -1301,7 +1494,7 @@ __global__ void check_sorted_kernel(const uint64_t *S, const int64_t *nS, uint32
 // ---------------------------------------------------------------------------
 struct WsLayout {
     size_t bufA, bufB, ids, segA, segB, fan1, fan2, spl1, spl2, tile_base, cbase, counts, sums, samples;
-    size_t nuniq, bstart, bcount, ucount, ncount, big, ufirst, uend, ucnt, scal;
+    size_t nuniq, bstart, bcount, ucount, ncount, big, big2, ufirst, uend, ucnt, scal;
     size_t total;
     int64_t max_counts, max_sums, n_final_slots;
 };
@@ -1345,6 +1538,7 @@ static WsLayout ws_layout(int64_t n) {
     L.ucount = take((size_t)(S2 + 1) * 8);
     L.ncount = take((size_t)(S2 + 1) * 8);
     L.big = take((size_t)S2 * 8);
+    L.big2 = take((size_t)S2 * 8);
     L.ufirst = take((size_t)(S2 + 1) * 4);
     L.uend = take((size_t)(S2 + 1) * 4);
     L.ucnt = take((size_t)(S1 + 2) * 8);
@@ -1508,8 +1702,12 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     SCI_LAUNCH(set_range_kernel<W>, dim3((unsigned)ceil_div(b.n_slots, 256)), dim3(256), 0, st, b);
     b.n_big = scal + 3;
     b.big = (int64_t *)(ws + L.big);
+    b.n_big2 = scal + 6;
+    b.big2 = (int64_t *)(ws + L.big2);
     SCI_HIP_TRY(launch_set_i64(b.n_big, 0, st));
+    SCI_HIP_TRY(launch_set_i64(b.n_big2, 0, st));
     SCI_LAUNCH(bucket_kernel<W>, dim3((unsigned)b.n_slots), dim3(kBThreads), 0, st, b);
+    SCI_LAUNCH(bucket_stream_kernel<W>, dim3((unsigned)n_cu), dim3(kBThreads), 0, st, b);
     SCI_LAUNCH(bucket_big_kernel<W>, dim3(4096), dim3(kDThreads), 0, st, b);
     SCI_HIP_TRY(hipGetLastError());
     SCI_HIP_TRY(device_scan(b.ucount, scal + 5, b.n_slots + 1, sums, scal + 0, st));

@@ -198,6 +198,26 @@ def test_dedup_heavy_hitters(W):
     _dedup_check(sci, np.repeat(few[:1], 300_000, axis=0), few[1:2][np.argsort([0])], W)
 
 
+@pytest.mark.parametrize("W", [1, 2])
+def test_dedup_heavy_hitter_among_dense_neighbours(W):
+    """One key repeated millions of times amid runs of distinct neighbours: the samples
+    are nearly all that key, so its final bucket also holds more distinct neighbours than
+    one LDS unit (the streamed unit gives way to the global-memory sort)."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(70 + W))
+    heavy = rng.integers(1 << 40, 1 << 62, size=W, dtype=np.int64).astype(np.uint64)
+    d = 40_000
+    offs = np.concatenate([-1 - np.arange(d), 1 + np.arange(d)]).astype(np.int64)
+    near = np.repeat(heavy[None, :], 2 * d, axis=0)
+    near[:, 0] = (near[:, 0].astype(np.int64) + offs).astype(np.uint64)
+    cand = np.concatenate([np.repeat(heavy[None, :], 4_000_000, axis=0), near])
+    cand = cand[rng.permutation(cand.shape[0])]
+    setin = si.sort_keys(np.concatenate([heavy[None, :], near[::97], _random_keys(rng, 500, W, pool=500)]))
+    setin = setin[np.concatenate([[True], np.any(setin[1:] != setin[:-1], axis=1)])]
+    say(f"dedup heavy among neighbours W={W} n={cand.shape[0]} set={setin.shape[0]}")
+    _dedup_check(sci, cand, setin, W)
+
+
 @pytest.mark.parametrize("name", ["tiny", "medium"])
 def test_dedup_of_generated_candidates(name):
     """Skewed real keys: coupled sets of a selected-set slice merged into the selected set."""
