@@ -41,8 +41,8 @@ def parse():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the large-workload streaming and energy/autograd timings")
-    ap.add_argument("--large-sources", type=int, default=4096)
-    ap.add_argument("--large-chunk", type=int, default=1 << 28)
+    ap.add_argument("--large-sources", type=int, default=32768)
+    ap.add_argument("--large-chunk", type=int, default=1 << 29)
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
     return ap.parse_args()
@@ -210,9 +210,10 @@ def batch_extras(args, torch, sci, si):
 
 
 def large_extras(args, torch, sci, si):
-    """Large workload (n_orb=60, 10a+10b, W=2): the first `large_sources` sources of S
-    streamed through the device pool (generation of chunk k+1 overlapping dedup-merge
-    of chunk k into S), and E / E+dE/dpsi over all of S, plain and through autograd."""
+    """Large workload (n_orb=60, 10a+10b, W=2): one mini-batch of `large_sources` sources
+    of S (32768 by default, over 1e10 candidates) streamed through the device pool
+    (generation of chunk k+1 overlapping dedup-merge of chunk k into S), and E / E+dE/dpsi
+    over all of S, plain and through autograd."""
     wl = si.WORKLOADS["large"]
     sysm = si.make_system(wl)
     dev = torch.device("cuda", 0)
@@ -223,13 +224,16 @@ def large_extras(args, torch, sci, si):
     dets = sel[:n_src]
     total = n_src * ham.n_coupled
     chunk = args.large_chunk
-    cap = total + n_sel
     W = ham.W
+    ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
+    # the two set buffers take what HBM has left (the union is far below the candidate count)
+    free_bytes = torch.cuda.mem_get_info(dev)[0]
+    cap = int(min(total + n_sel, (free_bytes - ws_bytes - (8 << 30)) // (2 * W * 8)))
     set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
     set_b = torch.empty_like(set_a)
     n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
     n_out = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws = torch.empty(sci.sci_stream_workspace_bytes(ham, chunk), dtype=torch.uint8, device=dev)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     flags = sci.new_flags(dev)
     gen_stream = torch.cuda.current_stream()
     dd_stream = torch.cuda.Stream()
@@ -255,7 +259,7 @@ def large_extras(args, torch, sci, si):
     del set_a, set_b, ws
     out = {
         "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
-                    f"first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
+                    f"one mini-batch of the first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
         "n_candidates": total, "n_unique_union": n_union, "ms": t_ms,
         "candidates_per_s": total / (t_ms / 1000.0),
         "kernel_ms": {k: round(v, 3) for k, v in sorted(kern.items(), key=lambda x: -x[1]) if v >= 0.05},
