@@ -3,9 +3,9 @@
 //
 // The paper's three steps map onto one device as follows:
 //   step 1 (local sort + regular sampling)  -> one sample per equal stratum of
-//          the candidates (hashed offset inside the stratum), sorted in LDS (or
-//          by one workgroup over global memory when there are more samples
-//          than fit), gives splitters at equal sample ranks;
+//          the candidates (hashed offset inside the stratum), sorted in LDS (more
+//          samples than fit: runs sorted by separate workgroups, then each sample
+//          ranked in their merged order), gives splitters at equal sample ranks;
 //   step 2 (splitters + binary search)       -> every key finds its bucket by
 //          binary search over the splitters held in LDS;
 //   step 3 (all-to-all + local merge/unique) -> a histogram/scan/scatter pass
@@ -327,7 +327,7 @@ struct LevelArgs {
     int64_t *cbase;          // [S_in + 1]
     int64_t *counts;         // [cbase[S_in]] per (segment, bucket, tile)
     int64_t max_tiles;       // grid bound
-    uint64_t *sample_buf;    // level-1 only: [max_samples][W] + scratch of the same size
+    uint64_t *sample_buf;    // level-1 only: [max_samples][W] sorted sample runs
 };
 
 __device__ __forceinline__ int64_t seg_size(const int64_t *seg, int s) { return seg[s + 1] - seg[s]; }
@@ -350,13 +350,12 @@ __device__ __forceinline__ int64_t sample_pos(int64_t start, int64_t size, int64
 
 // One workgroup per input segment: choose the fan-out, draw one sample per
 // stratum, sort them, pick splitters at equal sample ranks.
-template <int W, bool GLOBAL_SAMPLES>
+template <int W>
 __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     using C = DCfg<W>;
     __shared__ Key<W> s_buf[C::CAP];
     __shared__ Key<W> s_tmp[C::CAP];
     __shared__ RadixLds R;
-    __shared__ uint32_t gbase[256], dtot[256];
     const int s = blockIdx.x;
     const int64_t start = a.seg_in[s], size = seg_size(a.seg_in, s);
     int f = (int)std::min<int64_t>((int64_t)a.F, std::max<int64_t>(1, ceil_div_dev(size, a.target)));
@@ -364,34 +363,80 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     if (threadIdx.x == 0) a.fan[s] = f;
     if (f == 1) return;
     const int64_t M = std::min<int64_t>(size, std::min<int64_t>((int64_t)a.ovs * f, a.max_samples));
+    if (M > C::CAP) return;  // cannot happen: the host sorts larger samples in runs
     uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
-    if (!GLOBAL_SAMPLES) {
-        if (M > C::CAP) return;  // cannot happen: the host picks the global variant
-        for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
-            s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k, M));
+    for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
+        s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k, M));
+    }
+    __syncthreads();
+    const Key<W> ref = s_buf[0];
+    __syncthreads();
+    const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R);
+    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, (int)M, nbits, R);
+    for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
+        const int64_t r = ((int64_t)(j + 1) * M) / f;
+        store_key<W>(sp, j, res[r]);
+    }
+}
+
+// Splitters of one segment from more samples than one LDS sort holds (level 1).
+// Workgroup g sorts samples [g CAP, (g+1) CAP) in LDS and stores the sorted run
+// (section 4.1 step 1, local sort); sample_rank_kernel then places every sample in
+// the merged order of all runs, and those at splitter ranks are the splitters
+// (step 2).  They are the keys one sort of all samples would give.
+template <int W>
+__global__ __launch_bounds__(kDThreads) void sample_runs_kernel(LevelArgs a, int64_t n, int64_t M, int f) {
+    using C = DCfg<W>;
+    __shared__ Key<W> s_buf[C::CAP];
+    __shared__ Key<W> s_tmp[C::CAP];
+    __shared__ RadixLds R;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.fan[0] = f;
+    const int64_t k0 = (int64_t)blockIdx.x * C::CAP;
+    const int m = (int)std::min<int64_t>(C::CAP, M - k0);
+    for (int k = threadIdx.x; k < m; k += kDThreads) s_buf[k] = load_key<W>(a.in, sample_pos(0, n, k0 + k, M));
+    __syncthreads();
+    const Key<W> ref = s_buf[0];
+    __syncthreads();
+    const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, R);
+    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, m, nbits, R);
+    for (int k = threadIdx.x; k < m; k += kDThreads) store_key<W>(a.sample_buf, k0 + k, res[k]);
+}
+
+// One thread per sample: its rank in the stable merge of the sorted runs (keys of
+// earlier runs first among equals) is its index in its own run plus, in every other
+// run, the keys that come before it.  Ranks are distinct, so each splitter rank
+// (j+1) M / f has exactly one writer.
+template <int W>
+__global__ __launch_bounds__(kDThreads) void sample_rank_kernel(LevelArgs a, int64_t M, int f) {
+    using C = DCfg<W>;
+    const int64_t k = (int64_t)blockIdx.x * kDThreads + threadIdx.x;
+    if (k >= M) return;
+    const int n_runs = (int)ceil_div_dev(M, C::CAP);
+    const int g = (int)(k / C::CAP);
+    const Key<W> x = load_key<W>(a.sample_buf, k);
+    int64_t rank = k - (int64_t)g * C::CAP;
+    for (int h = 0; h < n_runs; ++h) {
+        if (h == g) continue;
+        const int64_t b0 = (int64_t)h * C::CAP;
+        int lo = 0, len = (int)std::min<int64_t>(C::CAP, M - b0);
+        while (len > 0) {
+            const int half = len >> 1;
+            const Key<W> y = load_key<W>(a.sample_buf, b0 + lo + half);
+            // before x: keys below it, and in earlier runs also keys equal to it
+            const bool before = (h < g) ? !key_less<W>(x, y) : key_less<W>(y, x);
+            if (before) {
+                lo += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
         }
-        __syncthreads();
-        const Key<W> ref = s_buf[0];
-        __syncthreads();
-        const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R);
-        Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, (int)M, nbits, R);
-        for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
-            const int64_t r = ((int64_t)(j + 1) * M) / f;
-            store_key<W>(sp, j, res[r]);
-        }
-    } else {
-        uint64_t *X = a.sample_buf, *Y = a.sample_buf + (int64_t)a.max_samples * W;
-        for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
-            store_key<W>(X, k, load_key<W>(a.in, sample_pos(start, size, k, M)));
-        }
-        __threadfence();
-        __syncthreads();
-        const int where = global_radix_sort<W>(X, X, Y, M, R, gbase, dtot);
-        const uint64_t *res = where ? Y : X;
-        for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
-            const int64_t r = ((int64_t)(j + 1) * M) / f;
-            store_key<W>(sp, j, load_key<W>(res, r));
-        }
+        rank += lo;
+    }
+    // M >= f, so at most one splitter index c has floor((c+1) M / f) == rank
+    const int64_t j = (rank * f) / M;
+    for (int64_t c = j - 1; c <= j; ++c) {
+        if (c >= 0 && c < f - 1 && ((c + 1) * M) / f == rank) store_key<W>(a.spl, c, x);
     }
 }
 
@@ -448,6 +493,23 @@ __device__ __forceinline__ int bucket_of(const Key<W> &k, const Key<W> *spl, int
     return lo;
 }
 
+// Lanes of one wave whose values in `b` are equal and adjacent form runs (keys in
+// generation order often share a bucket).  Returns the run's length at its first
+// lane (0 elsewhere) and that lane's index in *head.  Valid lanes form a prefix.
+__device__ __forceinline__ int wave_run(int b, bool valid, int *head) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int prev = __shfl_up(b, 1);
+    const bool is_head = valid && (lane == 0 || prev != b);
+    const uint64_t heads = __ballot(is_head);
+    const int nvalid = __popcll(__ballot(valid));
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    *head = 63 - __clzll((long long)(heads & upto));
+    if (!is_head) return 0;
+    const uint64_t later = heads & ~upto;
+    const int next = later ? __ffsll((long long)later) - 1 : nvalid;
+    return next - lane;
+}
+
 // Histogram pass: bucket id of every key (kept for the scatter pass) and the
 // per-(segment, bucket, tile) counts.
 template <int W, int FMAX>
@@ -501,10 +563,12 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (!ok[u]) continue;
             const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            int head;
+            const int len = wave_run(pos[u], ok[u], &head);
+            if (!ok[u]) continue;
             a.ids[i] = (uint16_t)pos[u];
-            atomicAdd(&s_cnt[pos[u]], 1u);
+            if (len) atomicAdd(&s_cnt[pos[u]], (uint32_t)len);
         }
     }
     __syncthreads();
@@ -1531,7 +1595,7 @@ static WsLayout ws_layout(int64_t n) {
     L.cbase = take((size_t)(S1 + 1) * 8);
     L.counts = take((size_t)L.max_counts * 8);
     L.sums = take((size_t)L.max_sums * 8);
-    L.samples = take((size_t)C::M1 * 2 * W * 8);
+    L.samples = take((size_t)C::M1 * W * 8);
     L.nuniq = take((size_t)S2 * 8);
     L.bstart = take((size_t)S2 * 8);
     L.bcount = take((size_t)S2 * 8);
@@ -1651,10 +1715,20 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             a.sample_buf = (uint64_t *)(ws + L.samples);
             const int64_t tiles_bound = ceil_div(n, a.tile) + S_cur;
             a.max_tiles = tiles_bound;
-            if (a.max_samples > C::CAP) {
-                SCI_LAUNCH((splitter_kernel<W, true>), dim3(S_cur), dim3(kDThreads), 0, st, a);
+            // the fan-out and sample count of the single level-1 segment are known here
+            int64_t n_smp = 0;
+            int fan0 = 1;
+            if (lvl == 0) {
+                fan0 = (int)std::min<int64_t>((int64_t)a.F, std::max<int64_t>(1, ceil_div_dev(n, a.target)));
+                n_smp = std::min<int64_t>(n, std::min<int64_t>((int64_t)a.ovs * fan0, a.max_samples));
+            }
+            if (lvl == 0 && fan0 > 1 && n_smp > C::CAP) {
+                SCI_LAUNCH(sample_runs_kernel<W>, dim3((unsigned)ceil_div(n_smp, C::CAP)), dim3(kDThreads), 0, st, a,
+                           n, n_smp, fan0);
+                SCI_LAUNCH(sample_rank_kernel<W>, dim3((unsigned)ceil_div(n_smp, kDThreads)), dim3(kDThreads), 0, st,
+                           a, n_smp, fan0);
             } else {
-                SCI_LAUNCH((splitter_kernel<W, false>), dim3(S_cur), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH(splitter_kernel<W>, dim3(S_cur), dim3(kDThreads), 0, st, a);
             }
             SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
             if (lvl == 0) {

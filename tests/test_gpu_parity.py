@@ -198,6 +198,47 @@ def test_dedup_heavy_hitters(W):
     _dedup_check(sci, np.repeat(few[:1], 300_000, axis=0), few[1:2][np.argsort([0])], W)
 
 
+@pytest.mark.parametrize("W,n_distinct,n_cand", [(1, 8_000_000, 110_000_000), (2, 2_000_000, 16_000_000)])
+def test_dedup_sample_runs_path(W, n_distinct, n_cand):
+    """Level-1 splitters from more samples than one LDS sort holds (sorted runs, then
+    each sample ranked in their merged order): every key of a known distinct set D
+    occurs at least once among n_cand candidates in random order, so the union is D
+    plus the set keys, and the novel keys are D minus the set."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(90 + W))
+    d = rng.integers(0, 2**63, size=(n_distinct, W), dtype=np.int64).astype(np.uint64)
+    d[: n_distinct // 2, -1] |= np.uint64(1) << np.uint64(63)
+    d = si.sort_keys(d)
+    d = d[np.concatenate([[True], np.any(d[1:] != d[:-1], axis=1)])]
+    extra = si.sort_keys(_random_keys(rng, 1000, W, pool=1000))
+    setin = si.sort_keys(np.concatenate([d[::7], extra]))
+    setin = setin[np.concatenate([[True], np.any(setin[1:] != setin[:-1], axis=1)])]
+    say(f"dedup sample-runs W={W} distinct={d.shape[0]} n={n_cand}")
+    dev = torch.device("cuda")
+    dd = sci.keys_to_device(d)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(91 + W)
+    idx = torch.cat([torch.arange(d.shape[0], device=dev),
+                     torch.randint(0, d.shape[0], (n_cand - d.shape[0],), device=dev, generator=gen)])
+    idx = idx[torch.randperm(n_cand, device=dev, generator=gen)]
+    cand = dd[idx].contiguous()
+    del idx
+    out, n_out, nov, n_nov, flags = sci.dedup_merge(cand, sci.keys_to_device(setin), W, want_novel=True)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "dedup") == 0
+    union = si.sort_keys(np.concatenate([d, setin]))
+    union = union[np.concatenate([[True], np.any(union[1:] != union[:-1], axis=1)])]
+    n = int(n_out.item())
+    assert n == union.shape[0]
+    assert torch.equal(out[:n], sci.keys_to_device(union))
+    # novel: the keys of D that are not set keys
+    row = np.dtype((np.void, 8 * W))
+    novel = d[~np.isin(np.ascontiguousarray(d).view(row).ravel(), np.ascontiguousarray(setin).view(row).ravel())]
+    m = int(n_nov.item())
+    assert m == novel.shape[0]
+    assert torch.equal(nov[:m], sci.keys_to_device(novel))
+
+
 @pytest.mark.parametrize("W", [1, 2])
 def test_dedup_heavy_hitter_among_dense_neighbours(W):
     """One key repeated millions of times amid runs of distinct neighbours: the samples
