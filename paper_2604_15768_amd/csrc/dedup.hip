@@ -1407,7 +1407,7 @@ __device__ int64_t wave_merge_path(const uint64_t *A, int64_t nA, const uint64_t
 }
 
 template <int W>
-__global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
+__global__ __launch_bounds__(kDThreads, 6) void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
     const int64_t s = blockIdx.x;  // unit
     if (s >= *a.n_units) return;
@@ -1441,83 +1441,92 @@ __global__ __launch_bounds__(kDThreads) void emit_kernel(EmitArgs a) {
     }
     // general case: merge the run with the set keys in this slot's range, one window of
     // kEmitStep outputs per round with both inputs staged in LDS.  Only window ends
-    // inside the merge need a split search over global memory.
+    // inside the merge need a split search over global memory; the four waves find
+    // those of up to kCutBatch windows at once before the windows are merged.
+    constexpr int kCutBatch = 64;
     __shared__ Key<W> sA[kEmitStep];
     __shared__ Key<W> sB[kEmitStep + 1];  // sB[0]: the set key just before the window
-    __shared__ int64_t s_cut;
+    __shared__ int64_t s_cut[kCutBatch];
+    const int wv = threadIdx.x / kWave;
+    const int64_t n_win = ceil_div_dev(total, kEmitStep);
     int64_t i0 = 0;  // run keys consumed by earlier windows
-    for (int64_t c0 = 0; c0 < total; c0 += kEmitStep) {
-        const int64_t c1 = c0 + kEmitStep < total ? c0 + kEmitStep : total;
-        if (threadIdx.x < kWave) {
+    for (int64_t w0 = 0; w0 < n_win; w0 += kCutBatch) {
+        const int nw = (int)(n_win - w0 < kCutBatch ? n_win - w0 : kCutBatch);
+        for (int q = wv; q < nw; q += kDWaves) {
+            const int64_t c1 = (w0 + q + 1) * kEmitStep < total ? (w0 + q + 1) * kEmitStep : total;
             const int64_t cut = (c1 == total) ? nA : wave_merge_path<W>(A, nA, Bs, nBs, c1);
-            if (threadIdx.x == 0) s_cut = cut;
+            if ((threadIdx.x & (kWave - 1)) == 0) s_cut[q] = cut;
         }
         __syncthreads();
-        const int64_t i1 = s_cut;
-        const int64_t j0 = c0 - i0;
-        const int na = (int)(i1 - i0), nb = (int)((c1 - i1) - j0);
-        for (int t = threadIdx.x; t < na; t += kDThreads) sA[t] = load_key<W>(A, i0 + t);
-        for (int t = threadIdx.x; t <= nb; t += kDThreads)
-            if (t > 0 || j0 > 0) sB[t] = load_key<W>(Bs, j0 - 1 + t);
-        __syncthreads();
-        const int p0 = threadIdx.x * kMergePer;
-        const int win = (int)(c1 - c0);
-        const int cnt = p0 < win ? (win - p0 < kMergePer ? win - p0 : kMergePer) : 0;
-        Key<W> vals[kMergePer];
-        uint32_t fa = 0, fd = 0;
-        if (cnt > 0) {
-            // run keys among this window's first p0 outputs (ties: set key first)
-            int lo = p0 > nb ? p0 - nb : 0, hi = p0 < na ? p0 : na;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (key_less<W>(sA[mid], sB[p0 - mid])) lo = mid + 1;
-                else hi = mid;
-            }
-            int i = lo, j = p0 - lo;
-#pragma unroll
-            for (int q = 0; q < kMergePer; ++q) {
-                if (q < cnt) {
-                    const bool takeA = i < na && (j >= nb || key_less<W>(sA[i], sB[1 + j]));
-                    if (takeA) {
-                        const Key<W> x = sA[i];
-                        vals[q] = x;
-                        fa |= 1u << q;
-                        // equal to the set key emitted just before it: already in the union
-                        if (j0 + j > 0 && key_eq<W>(sB[j], x)) fd |= 1u << q;
-                        ++i;
-                    } else {
-                        vals[q] = sB[1 + j];
-                        ++j;
+        for (int qw = 0; qw < nw; ++qw) {
+            const int64_t c0 = (w0 + qw) * kEmitStep;
+            const int64_t c1 = c0 + kEmitStep < total ? c0 + kEmitStep : total;
+            const int64_t i1 = s_cut[qw];
+            const int64_t j0 = c0 - i0;
+            const int na = (int)(i1 - i0), nb = (int)((c1 - i1) - j0);
+            for (int t = threadIdx.x; t < na; t += kDThreads) sA[t] = load_key<W>(A, i0 + t);
+            for (int t = threadIdx.x; t <= nb; t += kDThreads)
+                if (t > 0 || j0 > 0) sB[t] = load_key<W>(Bs, j0 - 1 + t);
+            __syncthreads();
+            const int p0 = threadIdx.x * kMergePer;
+            const int win = (int)(c1 - c0);
+            const int cnt = p0 < win ? (win - p0 < kMergePer ? win - p0 : kMergePer) : 0;
+            Key<W> vals[kMergePer];
+            uint32_t fa = 0, fd = 0;
+            if (cnt > 0) {
+                // run keys among this window's first p0 outputs (ties: set key first)
+                int lo = p0 > nb ? p0 - nb : 0, hi = p0 < na ? p0 : na;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (key_less<W>(sA[mid], sB[p0 - mid])) lo = mid + 1;
+                    else hi = mid;
+                }
+                int i = lo, j = p0 - lo;
+    #pragma unroll
+                for (int q = 0; q < kMergePer; ++q) {
+                    if (q < cnt) {
+                        const bool takeA = i < na && (j >= nb || key_less<W>(sA[i], sB[1 + j]));
+                        if (takeA) {
+                            const Key<W> x = sA[i];
+                            vals[q] = x;
+                            fa |= 1u << q;
+                            // equal to the set key emitted just before it: already in the union
+                            if (j0 + j > 0 && key_eq<W>(sB[j], x)) fd |= 1u << q;
+                            ++i;
+                        } else {
+                            vals[q] = sB[1 + j];
+                            ++j;
+                        }
                     }
                 }
             }
-        }
-        int lu = 0, ln = 0;
-#pragma unroll
-        for (int q = 0; q < kMergePer; ++q) {
-            const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
-            lu += (q < cnt) && !dup;
-            ln += (q < cnt) && fromA && !dup;
-        }
-        int64_t tu, tn;
-        const int64_t eu = block_excl_scan_i64(lu, &tu, wsum);
-        const int64_t en = block_excl_scan_i64(ln, &tn, wsum);
-        int64_t pu = ou + eu, pn = on + en;
-#pragma unroll
-        for (int q = 0; q < kMergePer; ++q) {
-            const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
-            if (q >= cnt || dup) continue;
-            if (pu < a.out_cap) store_key<W>(a.out, pu, vals[q]);
-            ++pu;
-            if (fromA) {
-                if (a.novel && pn < a.novel_cap) store_key<W>(a.novel, pn, vals[q]);
-                ++pn;
+            int lu = 0, ln = 0;
+    #pragma unroll
+            for (int q = 0; q < kMergePer; ++q) {
+                const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
+                lu += (q < cnt) && !dup;
+                ln += (q < cnt) && fromA && !dup;
             }
+            int64_t tu, tn;
+            const int64_t eu = block_excl_scan_i64(lu, &tu, wsum);
+            const int64_t en = block_excl_scan_i64(ln, &tn, wsum);
+            int64_t pu = ou + eu, pn = on + en;
+    #pragma unroll
+            for (int q = 0; q < kMergePer; ++q) {
+                const bool dup = (fd >> q) & 1u, fromA = (fa >> q) & 1u;
+                if (q >= cnt || dup) continue;
+                if (pu < a.out_cap) store_key<W>(a.out, pu, vals[q]);
+                ++pu;
+                if (fromA) {
+                    if (a.novel && pn < a.novel_cap) store_key<W>(a.novel, pn, vals[q]);
+                    ++pn;
+                }
+            }
+            ou += tu;
+            on += tn;
+            i0 = i1;
+            __syncthreads();  // the next window overwrites sA / sB (and the next batch s_cut)
         }
-        ou += tu;
-        on += tn;
-        i0 = i1;
-        __syncthreads();  // the next window overwrites sA / sB
     }
 }
 
