@@ -34,7 +34,7 @@ constexpr int kDWaves = kDThreads / kWave;
 
 template <int W>
 struct DCfg {
-    static constexpr int CAP = (W == 1) ? 4096 : 2048;     // LDS sort capacity (keys)
+    static constexpr int CAP = (W == 1) ? 3072 : 1536;     // LDS sort capacity (keys)
     static constexpr int K = CAP / kDThreads;              // keys per thread
     static constexpr int CH = CAP / kDWaves;               // keys per wave
     static constexpr int TARGET = CAP * 3 / 8;             // mean final bucket size (tail past CAP is rare)
@@ -1021,8 +1021,11 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
     }
 }
 
+// Three workgroups per CU: LDS holds 2 x 24 KB of keys for each (3,072 one-word or
+// 1,536 two-word keys), and at most 80 VGPRs leave room for their 24 waves.
 template <int W>
-__global__ __launch_bounds__(kBThreads) void bucket_kernel(BucketArgs a) {
+__global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
     __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
@@ -1186,11 +1189,13 @@ template <int W>
 __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) {
     using C = DCfg<W>;
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;
-    constexpr int kLogT = __builtin_ctz(4 * C::CAP);  // 4 CAP slots: load at most 1/2
-    constexpr uint32_t kTMask = (4u * C::CAP) - 1u;
+    // at least 4 CAP slots (a power of two): load at most 1/2
+    constexpr int kLogT = 32 - __builtin_clz(4u * C::CAP - 1u);
+    constexpr uint32_t kTSlots = 1u << kLogT;
+    constexpr uint32_t kTMask = kTSlots - 1u;
     __shared__ Key<W> s_in[C::CAP];     // the current chunk; radix ping-pong at the end
     __shared__ Key<W> s_uq[C::CAP];     // distinct keys so far
-    __shared__ uint32_t s_tab[2 * C::CAP];  // 16-bit slots: index < CAP in s_uq, CAP + i in s_in
+    __shared__ uint32_t s_tab[kTSlots / 2];  // 16-bit slots: index < CAP in s_uq, CAP + i in s_in
     __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];
     __shared__ uint64_t s_or[2];
     __shared__ int s_nu, s_over;
@@ -1203,7 +1208,7 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
         unit_span(a, s, start, size);
         const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
         const Key<W> ref = load_key<W>(a.src, start);
-        for (int i = threadIdx.x; i < 2 * C::CAP; i += kBThreads) s_tab[i] = 0xffffffffu;
+        for (int i = threadIdx.x; i < (int)(kTSlots / 2); i += kBThreads) s_tab[i] = 0xffffffffu;
         if (threadIdx.x == 0) {
             s_nu = 0;
             s_over = 0;
@@ -1233,10 +1238,10 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
                 const int i = k * kBThreads + threadIdx.x;
                 if (i >= m) continue;
                 uint32_t h = key_hash<W>(kk[k], kLogT);
-                // At most 2 CAP keys (CAP distinct so far, CAP in this chunk) occupy the 4 CAP
-                // slots, and each failed exchange follows another lane's insertion: the walk
-                // ends within 4 CAP visits plus 2 CAP retries.
-                for (int probe = 0; probe < 8 * C::CAP; ++probe) {
+                // At most 2 CAP keys (CAP distinct so far, CAP in this chunk) occupy the
+                // kTSlots >= 4 CAP slots, and each failed exchange follows another lane's
+                // insertion: the walk ends within kTSlots visits plus 2 CAP retries.
+                for (int probe = 0; probe < (int)kTSlots + 2 * C::CAP; ++probe) {
                     const uint32_t cur = s_tab[h >> 1];
                     const uint32_t v = (h & 1u) ? (cur >> 16) : (cur & 0xffffu);
                     if (v == 0xffffu) {
@@ -1407,7 +1412,8 @@ __device__ int64_t wave_merge_path(const uint64_t *A, int64_t nA, const uint64_t
 }
 
 template <int W>
-__global__ __launch_bounds__(kDThreads, 6) void emit_kernel(EmitArgs a) {
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(W == 1 ? 6 : 4, 8)))
+void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
     const int64_t s = blockIdx.x;  // unit
     if (s >= *a.n_units) return;
