@@ -243,8 +243,10 @@ def large_extras(args, torch, sci, si):
                              ws, ws.numel(), flags, gen_stream, dd_stream)
         torch.cuda.current_stream().wait_stream(dd_stream)
 
+    torch.cuda.reset_peak_memory_stats(dev)
     run()
     torch.cuda.synchronize()
+    peak_alloc = torch.cuda.max_memory_allocated(dev)
     sci.check_flags(flags, "large stream warmup")
     sci.sci_profile_read()
     sci.sci_profile_enable(True)
@@ -261,6 +263,8 @@ def large_extras(args, torch, sci, si):
         "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
                     f"one mini-batch of the first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
         "n_candidates": total, "n_unique_union": n_union, "ms": t_ms,
+        "device_bytes": {"pool_and_workspace": ws_bytes, "set_buffers": 2 * cap * W * 8,
+                         "peak_allocated": peak_alloc},
         "candidates_per_s": total / (t_ms / 1000.0),
         "kernel_ms": {k: round(v, 3) for k, v in sorted(kern.items(), key=lambda x: -x[1]) if v >= 0.05},
     }
@@ -280,6 +284,19 @@ def large_extras(args, torch, sci, si):
     return out, energy
 
 
+def _template_args(name, fam):
+    """Template arguments of `fam` in a kernel name, as strings ([] when not a template)."""
+    i = name.find(fam + "<")
+    if i < 0:
+        return []
+    j, depth = i + len(fam) + 1, 1
+    k = j
+    while k < len(name) and depth:
+        depth += {"<": 1, ">": -1}.get(name[k], 0)
+        k += 1
+    return [a.strip() for a in name[j:k - 1].split(",")]
+
+
 def recorded_traffic(kernel_name, W):
     """HBM bytes per launch of `kernel_name` from the committed PMC record, or None when
     there is none or the kernel's source file changed since the counters were taken."""
@@ -290,18 +307,59 @@ def recorded_traffic(kernel_name, W):
         return None
     rec = json.load(open(path))
     fam = kernel_name.strip("()").split("<")[0]
+    # the label's template arguments as the compiled kernel spells them
+    fan = {"C::F1": "4096", "C::F2": "512" if W == 1 else "256"}
+    want = [str(W) if a == "W" else fan.get(a, a) for a in _template_args(kernel_name, fam)]
     for name, e in rec.get("kernels", {}).items():
-        if e.get("family") != fam or f"{fam}<{W}" not in name:
+        if e.get("family") != fam or _template_args(name, fam) != want:
             continue
-        if fam in ("hist_kernel", "scatter_kernel"):  # two instantiations: match the fan-out
-            lvl = "4096" if "C::F1" in kernel_name else ("512" if W == 1 else "256")
-            if f", {lvl}>" not in name:
-                continue
         src = os.path.join(here, e["source"])
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != e["source_sha256"]:
             return None
         return e["read_bytes"] + e["write_bytes"]
     return None
+
+
+def copy_bandwidth(torch, dev, gib=4.0, reps=3):
+    """Read + write GB/s of a plain device-to-device copy of `gib` GiB (median of `reps`)."""
+    nel = int(gib * 2**30) // 8
+    a = torch.empty(nel, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nel * 8 / (float(np.median(ts)) / 1000.0) / 1e9
+
+
+def gen_dedup_traffic(per_kernel, W, stage_ms, copy_gbps):
+    """HBM bytes the counters recorded for the generation and dedup kernels of one step
+    (PMC FETCH_SIZE + WRITE_SIZE, calibrated, per launch) over the two stages' time.
+    Kernels without a current record (small ones, or source changed since the counters
+    were taken) are left out; `time_covered` is the share of kernel time that has one."""
+    tot_bytes, covered_ms, all_ms = 0.0, 0.0, 0.0
+    for name, k in per_kernel.items():
+        if "hpsi" in name or "reduce" in name or "grad" in name:
+            continue  # energy stage
+        ms = k["ms_per_launch"] * k["launches_per_step"]
+        all_ms += ms
+        b = recorded_traffic(name, W)
+        if b is not None:
+            tot_bytes += b * k["launches_per_step"]
+            covered_ms += ms
+    if covered_ms == 0.0:
+        return None
+    gbps = tot_bytes / (stage_ms / 1000.0) / 1e9
+    return {"bytes_per_step": tot_bytes, "stage_ms": stage_ms, "achieved": gbps, "unit": "GB/s",
+            "frac_of_peak": gbps / HBM_PEAK_GBS, "peak": HBM_PEAK_GBS,
+            "copy_GBps": copy_gbps, "frac_of_copy": gbps / copy_gbps, "time_covered": covered_ms / all_ms}
 
 
 def cpu_baseline(sysm, n_src):
@@ -366,6 +424,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    # bandwidth a plain device copy reaches here (read + write), the practical ceiling
+    copy_gbps = copy_bandwidth(torch, dev)
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
@@ -468,6 +529,7 @@ def main():
         "kernels": per_kernel,
         "gen_roofline": {"bound": "hbm", "achieved": gen_bytes / (g_ms / 1000.0) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gen_bytes / (g_ms / 1000.0) / 1e9 / HBM_PEAK_GBS},
+        "gen_dedup_hbm": gen_dedup_traffic(per_kernel, W, g_ms + d_ms, copy_gbps),
     }
     if not args.no_extras:
         result["extras"] = {"reverse_index_topk": select_extras(torch, sci, keys, n_cand, set_out, n_set_out,
