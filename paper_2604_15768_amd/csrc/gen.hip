@@ -77,10 +77,55 @@ __device__ __forceinline__ Key<W> uni_key(const Key<W> &k) {
     return r;
 }
 
-// Write one output slot (dense) or compact it through one atomic per wave (screened).
+// Screened output is staged per wave: kept entries collect in LDS and leave with one
+// atomic on the output counter per kStage entries, not one per wave-wide batch (the
+// counter is a single address every workgroup of the launch updates).
+constexpr int kStage = 512;
+
+template <int W>
+struct GenStage {
+    Key<W> key[kGenThreads / kWave][kStage];
+    double hij[kGenThreads / kWave][kStage];
+    int fill[kGenThreads / kWave];  // entries left in each wave's stage at the end of a source
+    unsigned long long base;        // their output range, reserved once per workgroup
+};
+
+// LDS written by some lanes of a wave is read by others: order the accesses
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Write this wave's staged entries (all of one source) at a reserved output range.
+template <int W>
+__device__ __forceinline__ void flush_stage(const GenArgs &a, GenStage<W> *st, int &fill, int64_t src) {
+    if (fill == 0) return;  // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    wave_lds_sync();
+    unsigned long long base = 0;
+    if (lane == 0) {
+        base = atomicAdd(a.n_out, (unsigned long long)fill);
+        if ((int64_t)(base + fill) > a.capacity) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
+    }
+    base = __shfl(base, 0);
+    for (int i = lane; i < fill; i += kWave) {
+        const int64_t o = (int64_t)base + i;
+        if (o < a.capacity) {
+            store_key<W>(a.keys, o, st->key[w][i]);
+            a.hij[o] = st->hij[w][i];
+            a.src_out[o] = (int32_t)src;
+        }
+    }
+    wave_lds_sync();  // every lane has read the stage before it is refilled
+    fill = 0;
+}
+
+// Write one output slot (dense) or stage it for compaction (screened); called by
+// whole waves.
 template <int W, bool DENSE>
 __device__ __forceinline__ void emit(const GenArgs &a, int64_t o_dense, bool valid, const Key<W> &key, double h,
-                                     int64_t src) {
+                                     int64_t src, GenStage<W> *st, int &fill) {
     if constexpr (DENSE) {
         if (valid) {
             store_key<W>(a.keys, o_dense, key);
@@ -91,21 +136,15 @@ __device__ __forceinline__ void emit(const GenArgs &a, int64_t o_dense, bool val
         const bool keep = valid && fabs(h) > a.eps;
         const unsigned long long m = __ballot(keep);
         if (m == 0ull) return;
-        const int lane = threadIdx.x & (kWave - 1);
-        unsigned long long base = 0;
-        if (lane == 0) {
-            base = atomicAdd(a.n_out, (unsigned long long)__popcll(m));
-            if ((int64_t)(base + __popcll(m)) > a.capacity) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
-        }
-        base = __shfl(base, 0);
+        const int c = __popcll(m);
+        if (fill + c > kStage) flush_stage<W>(a, st, fill, src);
         if (keep) {
-            const int64_t o = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
-            if (o < a.capacity) {
-                store_key<W>(a.keys, o, key);
-                a.hij[o] = h;
-                a.src_out[o] = (int32_t)src;
-            }
+            const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+            const int i = fill + __popcll(m & ((1ull << lane) - 1ull));
+            st->key[w][i] = key;
+            st->hij[w][i] = h;
         }
+        fill += c;
     }
 }
 
@@ -116,7 +155,8 @@ __device__ __forceinline__ void emit(const GenArgs &a, int64_t o_dense, bool val
 // quantity (row key, integral row base, per-particle sign bits gathered with a
 // ballot) is wave-uniform and lanes walk the particle index without division.
 template <int W, bool DENSE>
-__device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, GenLds &L) {
+__device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, GenLds &L, GenStage<W> *st) {
+    int fill = 0;  // screened entries staged by this wave
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t flat0 = src * a.nc;
@@ -243,7 +283,7 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
                     }
                     h = (par & 1) ? -v : v;
                 }
-                emit<W, DENSE>(a, obase + rb + t, valid, key, h, src);
+                emit<W, DENSE>(a, obase + rb + t, valid, key, h, src, st, fill);
             }
         } else if (g < g4) {
             // same-spin doubles p<q -> a<b
@@ -296,7 +336,7 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
                     Key<W> key = rk;
                     key_flip<W>(key, ta[u] + off);
                     key_flip<W>(key, tb[u] + off);
-                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src);
+                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src, st, fill);
                 }
             }
         } else {
@@ -358,8 +398,31 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
                     Key<W> key = rk;
                     key_flip<W>(key, ta[u]);
                     key_flip<W>(key, tb[u] + n);
-                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src);
+                    emit<W, DENSE>(a, obase + rb + tu, tu < t1, key, par[u] ? -v[u] : v[u], src, st, fill);
                 }
+            }
+        }
+    }
+    if constexpr (!DENSE) {
+        // what the waves still hold leaves with one reservation for the workgroup
+        const int w = tid / kWave;
+        if (lane == 0) st->fill[w] = fill;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long tot = 0;
+            for (int x = 0; x < kGenThreads / kWave; ++x) tot += (unsigned long long)st->fill[x];
+            st->base = tot ? atomicAdd(a.n_out, tot) : 0ull;
+            if (tot && (int64_t)(st->base + tot) > a.capacity) atomicOr(a.flags, SCI_FLAG_OVERFLOW);
+        }
+        __syncthreads();
+        unsigned long long b0 = st->base;
+        for (int x = 0; x < w; ++x) b0 += (unsigned long long)st->fill[x];
+        for (int i = lane; i < fill; i += kWave) {
+            const int64_t o = (int64_t)b0 + i;
+            if (o < a.capacity) {
+                store_key<W>(a.keys, o, st->key[w][i]);
+                a.hij[o] = st->hij[w][i];
+                a.src_out[o] = (int32_t)src;
             }
         }
     }
@@ -380,7 +443,13 @@ __device__ __forceinline__ int64_t xcd_local_block(int64_t b, int64_t n) {
 template <int W, bool DENSE>
 __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
     __shared__ GenLds L;
-    gen_source<W, DENSE>(a, a.src_first + xcd_local_block(blockIdx.x, gridDim.x), L);
+    const int64_t src = a.src_first + xcd_local_block(blockIdx.x, gridDim.x);
+    if constexpr (DENSE) {
+        gen_source<W, true>(a, src, L, nullptr);
+    } else {
+        __shared__ GenStage<W> st;
+        gen_source<W, false>(a, src, L, &st);
+    }
 }
 
 // A tile: n_src consecutive sources of one system of a batch.
@@ -413,7 +482,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_batched_kernel(const GenArgs 
         const GenArgs &a = items[tile.item];
         for (int j = 0; j < tile.n_src; ++j) {
             if (j > 0) __syncthreads();
-            gen_source<W, true>(a, tile.src0 + j, L);
+            gen_source<W, true>(a, tile.src0 + j, L, nullptr);
         }
     }
 }
