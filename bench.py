@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the large-workload streaming and energy/autograd timings")
     ap.add_argument("--large-sources", type=int, default=32768)
-    ap.add_argument("--large-chunk", type=int, default=1 << 29)
+    ap.add_argument("--large-chunk", type=int, default=0, help="pool chunk (candidates); 0: pick the fastest of 2^28..2^30")
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
     return ap.parse_args()
@@ -254,9 +254,9 @@ def large_extras(args, torch, sci, si):
     n_src = min(args.large_sources, n_sel)
     dets = sel[:n_src]
     total = n_src * ham.n_coupled
-    chunk = args.large_chunk
+    chunks = [args.large_chunk] if args.large_chunk > 0 else [1 << 28, 1 << 29, 1 << 30]
     W = ham.W
-    ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
+    ws_bytes = max(sci.sci_stream_workspace_bytes(ham, c) for c in chunks)
     # the two set buffers take what HBM has left (the union is far below the candidate count)
     free_bytes = torch.cuda.mem_get_info(dev)[0]
     cap = int(min(total + n_sel, (free_bytes - ws_bytes - (8 << 30)) // (2 * W * 8)))
@@ -269,16 +269,22 @@ def large_extras(args, torch, sci, si):
     gen_stream = torch.cuda.current_stream()
     dd_stream = torch.cuda.Stream()
 
-    def run():
-        sci.sci_stream_dedup(ham, dets, n_src, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out,
+    def run_chunk(c):
+        sci.sci_stream_dedup(ham, dets, n_src, 0, total, c, sel, n_in, set_a, set_b, cap, n_out,
                              ws, ws.numel(), flags, gen_stream, dd_stream)
         torch.cuda.current_stream().wait_stream(dd_stream)
 
+    # pool chunk: the fastest of the candidates, one timed pass each after a warm-up pass
     torch.cuda.reset_peak_memory_stats(dev)
-    run()
-    torch.cuda.synchronize()
+    sweep = {}
+    for c in chunks:
+        run_chunk(c)
+        torch.cuda.synchronize()
+        sci.check_flags(flags, "large stream warmup")
+        sweep[c] = _median_ms(lambda: run_chunk(c), 1, torch)
     peak_alloc = torch.cuda.max_memory_allocated(dev)
-    sci.check_flags(flags, "large stream warmup")
+    chunk = min(sweep, key=sweep.get)
+    run = lambda: run_chunk(chunk)
     sci.sci_profile_read()
     sci.sci_profile_enable(True)
     t_ms = _median_ms(run, 3, torch)
@@ -294,6 +300,7 @@ def large_extras(args, torch, sci, si):
         "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
                     f"one mini-batch of the first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
         "n_candidates": total, "n_unique_union": n_union, "ms": t_ms,
+        "chunk": chunk, "chunk_sweep_ms": {str(c): round(v, 1) for c, v in sweep.items()},
         "device_bytes": {"pool_and_workspace": ws_bytes, "set_buffers": 2 * cap * W * 8,
                          "peak_allocated": peak_alloc},
         "candidates_per_s": total / (t_ms / 1000.0),
