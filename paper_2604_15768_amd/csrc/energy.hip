@@ -26,7 +26,7 @@ constexpr int kRedThreads = 256;
 
 struct EnergyArgs {
     int n, na, nb;
-    const double *h1, *eri, *vdir, *vanti, *jmat, *kmat;
+    const double *h1, *eri, *vdir, *vanti, *jmat, *kmat, *jtpq, *ktpq;
     const uint64_t *sel;
     int64_t n_sel;
     const double *psi;
@@ -77,6 +77,8 @@ __device__ double offdiag_elem(const EnergyArgs &a, const Key<W> &bra, const Key
         const int p = P - sg * n, t = A - sg * n;
         const int par = key_popc_below<W>(ket, P) + key_popc_below<W>(ket, A) - (P < A ? 1 : 0);
         double v = a.h1[t * n + p];
+        const double *jr = a.jtpq + (int64_t)(t * n + p) * n;  // (tp|qq) over q
+        const double *kr = a.ktpq + (int64_t)(t * n + p) * n;  // (tq|qp) over q
         // occupied spin orbitals of the ket in ascending order (alpha block, then beta)
         Key<W> occ = ket;
         while (true) {
@@ -86,8 +88,8 @@ __device__ double offdiag_elem(const EnergyArgs &a, const Key<W> &bra, const Key
             if (Q == P) continue;
             const int s2 = Q >= n ? 1 : 0;
             const int q = Q - s2 * n;
-            const double jv = a.eri[((int64_t)(t * n + p) * n + q) * n + q];
-            const double kv = (s2 == sg) ? a.eri[((int64_t)(t * n + q) * n + q) * n + p] : 0.0;
+            const double jv = jr[q];
+            const double kv = (s2 == sg) ? kr[q] : 0.0;
             v += jv - kv;
         }
         return (par & 1) ? -v : v;
@@ -409,6 +411,8 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
     a.vanti = d.vanti;
     a.jmat = d.jmat;
     a.kmat = d.kmat;
+    a.jtpq = d.jtpq;
+    a.ktpq = d.ktpq;
     a.sel = sel;
     a.n_sel = n_sel;
     a.psi = psi;
@@ -584,6 +588,8 @@ extern "C" int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t
         a.vanti = d.vanti;
         a.jmat = d.jmat;
         a.kmat = d.kmat;
+        a.jtpq = d.jtpq;
+        a.ktpq = d.ktpq;
         a.sel = it.sel;
         a.n_sel = n_sel;
         a.psi = it.psi;

@@ -30,7 +30,7 @@ struct GenArgs {
     int W;
     int n, na, nb, va, vb;
     int c1, c2, c3, c4, nc;
-    const double *h1, *eri, *vdir, *vanti;
+    const double *h1, *eri, *vdir, *vanti, *jtpq, *ktpq;
     const uint16_t *pairs[4];
     // tiles
     const uint64_t *dets;
@@ -209,12 +209,13 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
             double v = a.h1[t * n + p];
             for (int s2 = 0; s2 < 2; ++s2) {
                 const int cnt = s2 ? a.nb : a.na;
-                const double *jrow = a.eri + (int64_t)(t * n + p) * n * n;
+                const double *jr = a.jtpq + (int64_t)(t * n + p) * n;  // (tp|qq) over q
+                const double *kr = a.ktpq + (int64_t)(t * n + p) * n;  // (tq|qp) over q
                 for (int k = 0; k < cnt; ++k) {
                     const int q = L.occ[s2][k];
                     if (s2 == sg && q == p) continue;
-                    const double j = jrow[q * n + q];
-                    const double kx = (s2 == sg) ? a.eri[((int64_t)(t * n + q) * n + q) * n + p] : 0.0;
+                    const double j = jr[q];
+                    const double kx = (s2 == sg) ? kr[q] : 0.0;
                     v += j - kx;
                 }
             }
@@ -276,8 +277,8 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
                         for (int k = 0; k < cnt; ++k) {
                             const int q = L.occ[s2][k];
                             if (s2 == sg && q == p) continue;
-                            const double j = a.eri[((int64_t)(ta * n + p) * n + q) * n + q];
-                            const double kx = (s2 == sg) ? a.eri[((int64_t)(ta * n + q) * n + q) * n + p] : 0.0;
+                            const double j = a.jtpq[(int64_t)(ta * n + p) * n + q];
+                            const double kx = (s2 == sg) ? a.ktpq[(int64_t)(ta * n + p) * n + q] : 0.0;
                             v += j - kx;
                         }
                     }
@@ -506,6 +507,8 @@ static GenArgs make_gen_args(const HamDev &d, const uint64_t *dets, int64_t exc_
     a.eri = d.eri;
     a.vdir = d.vdir;
     a.vanti = d.vanti;
+    a.jtpq = d.jtpq;
+    a.ktpq = d.ktpq;
     for (int t = 0; t < 4; ++t) a.pairs[t] = d.pairs[t];
     a.dets = dets;
     a.src_first = exc_begin / d.n_coupled;

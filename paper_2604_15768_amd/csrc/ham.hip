@@ -31,11 +31,13 @@ int32_t fail(int32_t status, const char *fmt, ...) {
     return status;
 }
 
-// vdir[p][q][a][b] = (ap|bq); vanti[p][q][a][b] = (ap|bq) - (aq|bp)
+// vdir[p][q][a][b] = (ap|bq); vanti[p][q][a][b] = (ap|bq) - (aq|bp);
+// jtpq[t][p][q] = (tp|qq), ktpq[t][p][q] = (tq|qp).
 // One thread per output element; grid covers n^4 exactly (bounds-checked).
 __global__ void build_tables_kernel(const double *__restrict__ eri, double *__restrict__ vdir,
                                     double *__restrict__ vanti, double *__restrict__ jmat,
-                                    double *__restrict__ kmat, int n) {
+                                    double *__restrict__ kmat, double *__restrict__ jtpq,
+                                    double *__restrict__ ktpq, int n) {
     const int64_t n2 = (int64_t)n * n;
     const int64_t total = n2 * n2;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,6 +50,13 @@ __global__ void build_tables_kernel(const double *__restrict__ eri, double *__re
         const double x = eri[((int64_t)(a * n + q) * n + b) * n + p];  // (aq|bp)
         vdir[t] = d;
         vanti[t] = d - x;
+    }
+    if (t < n2 * n) {
+        const int q = (int)(t % n);
+        const int p = (int)((t / n) % n);
+        const int tt = (int)(t / n2);
+        jtpq[t] = eri[((int64_t)(tt * n + p) * n + q) * n + q];  // (tp|qq)
+        ktpq[t] = eri[((int64_t)(tt * n + q) * n + q) * n + p];  // (tq|qp)
     }
     if (t < n2) {
         const int p = (int)(t / n), q = (int)(t % n);
@@ -167,9 +176,11 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
     const int64_t off_vanti = off_vdir + align(n4 * 8);
     const int64_t off_j = off_vanti + align(n4 * 8);
     const int64_t off_k = off_j + align(n2 * 8);
+    const int64_t off_jt = off_k + align(n2 * 8);
+    const int64_t off_kt = off_jt + align(n2 * n * 8);
     const int pair_m[4] = {n_alpha, n_beta, n_orb - n_alpha, n_orb - n_beta};
     int64_t off_pairs[4];
-    int64_t cursor = off_k + align(n2 * 8);
+    int64_t cursor = off_kt + align(n2 * n * 8);
     for (int t = 0; t < 4; ++t) {
         off_pairs[t] = cursor;
         cursor += align(std::max<int64_t>(1, comb2(pair_m[t])) * 2);
@@ -202,7 +213,7 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
     SCI_LAUNCH(build_tables_kernel, dim3((unsigned)blocks), dim3(threads), 0, 0,
                        (const double *)(base + off_eri), (double *)(base + off_vdir),
                        (double *)(base + off_vanti), (double *)(base + off_j),
-                       (double *)(base + off_k), (int)n);
+                       (double *)(base + off_k), (double *)(base + off_jt), (double *)(base + off_kt), (int)n);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return cleanup(fail(SCI_EHIP, "sci_ham_create: table build failed"));
 
@@ -226,6 +237,8 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
     d.vanti = (const double *)(base + off_vanti);
     d.jmat = (const double *)(base + off_j);
     d.kmat = (const double *)(base + off_k);
+    d.jtpq = (const double *)(base + off_jt);
+    d.ktpq = (const double *)(base + off_kt);
     for (int t = 0; t < 4; ++t) d.pairs[t] = (const uint16_t *)(base + off_pairs[t]);
     h->block = block;
     *out = h;

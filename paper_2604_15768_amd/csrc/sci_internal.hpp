@@ -31,6 +31,8 @@ struct HamDev {
     const double *vanti; // [p][q][a][b] = (ap|bq) - (aq|bp)
     const double *jmat;  // [p][q] = (pp|qq)
     const double *kmat;  // [p][q] = (pq|qp)
+    const double *jtpq;  // [t][p][q] = (tp|qq): the Coulomb sum of a single t <- p is a row over q
+    const double *ktpq;  // [t][p][q] = (tq|qp): its exchange sum, also a row over q
     // lexicographic pairs (i<j) of m items as i | j<<8, for m = n_alpha,
     // n_beta, v_alpha, v_beta (index 0..3)
     const uint16_t *pairs[4];
