@@ -957,16 +957,20 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
     // this wave's output offset per digit: all keys of smaller digits, plus
     // keys of this digit held by lower waves (each wave computes its own row)
     // (each lane holds digits 4*lane .. 4*lane+3: one 8-byte LDS read per wave row)
-    uint32_t tot[4] = {0u, 0u, 0u, 0u}, pre[4], low[4] = {0u, 0u, 0u, 0u};
+    // the four 16-bit fields add without carries: no digit count exceeds the unit's keys
+    static_assert(kBK * kBThreads < 65536, "digit counts must fit 16 bits");
+    uint64_t tot4 = 0, low4 = 0;
 #pragma unroll
     for (int ww = 0; ww < kBWaves; ++ww) {
         const uint64_t c4 = *reinterpret_cast<const uint64_t *>(&s_cnt[ww][4 * lane]);
+        tot4 += c4;
+        low4 += (ww < w) ? c4 : 0ull;
+    }
+    uint32_t tot[4], pre[4], low[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t c = (uint32_t)(c4 >> (16 * j)) & 0xffffu;
-            tot[j] += c;
-            low[j] += (ww < w) ? c : 0u;
-        }
+    for (int j = 0; j < 4; ++j) {
+        tot[j] = (uint32_t)(tot4 >> (16 * j)) & 0xffffu;
+        low[j] = (uint32_t)(low4 >> (16 * j)) & 0xffffu;
     }
     wave_scan256(tot, pre);
     __syncthreads();  // every wave has read the counts before rows are overwritten
