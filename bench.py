@@ -393,7 +393,7 @@ def gen_dedup_traffic(per_kernel, W, stage_ms, copy_gbps):
             tot_bytes += b * k["launches_per_step"]
             covered_ms += ms
     if covered_ms == 0.0:
-        return None
+        return {"bytes_per_step": None, "achieved": None, "copy_GBps": copy_gbps, "time_covered": 0.0}
     gbps = tot_bytes / (stage_ms / 1000.0) / 1e9
     return {"bytes_per_step": tot_bytes, "stage_ms": stage_ms, "achieved": gbps, "unit": "GB/s",
             "frac_of_peak": gbps / HBM_PEAK_GBS, "peak": HBM_PEAK_GBS,
