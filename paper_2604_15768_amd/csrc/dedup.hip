@@ -577,8 +577,14 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
 }
 
 // Scatter pass: each key to its bucket's range (order inside a bucket is free).
+// The scatter pass runs 1,024-thread workgroups, two per CU: the open output runs
+// stay one per bucket per workgroup while twice as many loads are in flight as with
+// 512 threads (level-2 scatter 16.4 -> 15.3 ms on the medium workload).
+constexpr int kSThreads = 1024;
+
 template <int W, int FMAX>
-__global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
+__global__ __launch_bounds__(kSThreads) void scatter_kernel(LevelArgs a) {
+    constexpr int kT = kSThreads;
     // each bucket's output cursor for this tile: positions are below n < 2^32 (the entry
     // point refuses larger inputs), so 32 bits hold them and the LDS stays small
     __shared__ uint32_t s_cur[FMAX];
@@ -594,15 +600,15 @@ __global__ __launch_bounds__(kDThreads) void scatter_kernel(LevelArgs a) {
         const int64_t start = a.seg_in[s] + t * a.tile;
         const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
         const int64_t *cp = a.counts + a.cbase[s];
-        for (int j = threadIdx.x; j < f; j += kDThreads) s_cur[j] = (uint32_t)cp[(int64_t)j * T + t];
+        for (int j = threadIdx.x; j < f; j += kT) s_cur[j] = (uint32_t)cp[(int64_t)j * T + t];
         __syncthreads();
         constexpr int U = 8;
-        for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kDThreads) {
+        for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kT) {
             Key<W> k[U];
             int b[U];
     #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t i = i0 + u * kDThreads + threadIdx.x;
+                const int64_t i = i0 + u * kT + threadIdx.x;
                 b[u] = -1;
                 if (i < end) {
                     b[u] = a.ids[i];
@@ -1761,10 +1767,10 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 2, st));
             if (lvl == 0) {
                 SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
-                           dim3(kDThreads), 0, st, a);
+                           dim3(kSThreads), 0, st, a);
             } else {
                 SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
-                           dim3(kDThreads), 0, st, a);
+                           dim3(kSThreads), 0, st, a);
             }
             const int64_t slots = (int64_t)S_cur * a.F;
             SCI_LAUNCH(next_segments_kernel, dim3((unsigned)ceil_div(slots + 1, 256)), dim3(256), 0, st, a, n);
