@@ -512,8 +512,14 @@ __device__ __forceinline__ int wave_run(int b, bool valid, int *head) {
 
 // Histogram pass: bucket id of every key (kept for the scatter pass) and the
 // per-(segment, bucket, tile) counts.
+// 1,024-thread workgroups: the LDS of a tile (its splitters and counters) serves four
+// times the waves of a 256-thread one, which hide the latency of the conflicting
+// splitter reads (level 1: 10.6 -> 9.7 ms on the medium workload).
+constexpr int kHThreads = 1024;
+
 template <int W, int FMAX>
-__global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
+__global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
+    constexpr int kH = kHThreads;
     __shared__ Key<W> s_spl[FMAX - 1];
     __shared__ uint32_t s_cnt[FMAX];
     const int64_t g = blockIdx.x;
@@ -527,23 +533,23 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
     const uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
     // splitters padded to FMAX-1 with the all-ones key, which no key is above: every
     // search below takes exactly log2(FMAX) steps with no bounds checks
-    for (int j = threadIdx.x; j < FMAX - 1; j += kDThreads) {
+    for (int j = threadIdx.x; j < FMAX - 1; j += kH) {
         if (j < f - 1) s_spl[j] = load_key<W>(sp, j);
         else {
 #pragma unroll
             for (int q = 0; q < W; ++q) s_spl[j].w[q] = ~0ull;
         }
     }
-    for (int j = threadIdx.x; j < f; j += kDThreads) s_cnt[j] = 0;
+    for (int j = threadIdx.x; j < f; j += kH) s_cnt[j] = 0;
     __syncthreads();
     constexpr int kSteps = __builtin_ctz(FMAX);
-    for (int64_t i0 = start; i0 < end; i0 += 4 * kDThreads) {
+    for (int64_t i0 = start; i0 < end; i0 += 4 * kH) {
         Key<W> k[4];
         int pos[4];
         bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            const int64_t i = i0 + u * kH + threadIdx.x;
             ok[u] = i < end;
             if (ok[u]) k[u] = load_key<W>(a.in, i);
             else {
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u * kDThreads + threadIdx.x;
+            const int64_t i = i0 + u * kH + threadIdx.x;
             int head;
             const int len = wave_run(pos[u], ok[u], &head);
             if (!ok[u]) continue;
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(kDThreads) void hist_kernel(LevelArgs a) {
     }
     __syncthreads();
     int64_t *cp = a.counts + a.cbase[s];
-    for (int j = threadIdx.x; j < f; j += kDThreads) cp[(int64_t)j * T + t] = s_cnt[j];
+    for (int j = threadIdx.x; j < f; j += kH) cp[(int64_t)j * T + t] = s_cnt[j];
 }
 
 // Scatter pass: each key to its bucket's range (order inside a bucket is free).
@@ -1757,9 +1763,9 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             }
             SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
             if (lvl == 0) {
-                SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kHThreads), 0, st, a);
             } else {
-                SCI_LAUNCH((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kDThreads), 0, st, a);
+                SCI_LAUNCH((hist_kernel<W, C::F2>), dim3((unsigned)tiles_bound), dim3(kHThreads), 0, st, a);
             }
             SCI_HIP_TRY(hipGetLastError());
             // exclusive scan of all counters -> absolute output offsets
