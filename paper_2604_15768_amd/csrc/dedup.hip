@@ -1339,9 +1339,10 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
     }
 }
 
-// Oversized buckets (skewed or heavily repeated keys): one workgroup per listed
-// slot sorts over global memory with the same radix ranking, then run-length
-// unique; fixed grid, slots taken in grid-stride order from the device list.
+// Oversized units with more distinct keys than LDS holds (the streaming kernel
+// above passes them on): one workgroup per listed unit sorts over global memory
+// with the same radix ranking, then run-length unique; fixed grid, units taken in
+// grid-stride order from the device list.
 template <int W>
 __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
     __shared__ BucketLds L;
