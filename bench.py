@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--workload", default="medium", choices=["tiny", "medium"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=8000)
+    ap.add_argument("--cpu-single-sources", type=int, default=500,
+                    help="sources of the single-thread oracle sample (0: skip)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time only the oracle on --cpu-sources sources and print it (no GPU)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
@@ -418,11 +422,27 @@ def cpu_baseline(sysm, n_src):
                       f"sources: generation ({n_cand} candidates), dedup into S, H psi rows; {dt:.1f} s"}
 
 
+def single_thread_baseline(n_src):
+    """The oracle on one host thread, timed in a child process (OpenMP fixes its thread
+    count when the library loads); the child runs only the CPU oracle."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--cpu-sources", str(n_src)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_only:
+        import sci_inputs as si
+        print(json.dumps(cpu_baseline(si.make_system(si.WORKLOADS[args.workload]), args.cpu_sources)), flush=True)
+        return
     import torch
 
     import paper_2604_15768_amd as sci
@@ -583,6 +603,8 @@ def main():
         result["extras"].update({"batched_generation": bg, "batched_energy": be})
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, args.cpu_sources)
+        if args.cpu_single_sources > 0:
+            result["cpu_baseline"]["single_thread"] = single_thread_baseline(args.cpu_single_sources)
     print(json.dumps(result), flush=True)
 
 
