@@ -896,15 +896,17 @@ __device__ __forceinline__ uint32_t key_hash(const Key<W> &k, int log_t) {
     return (y * 0x9E3779B1u) >> (32 - log_t);
 }
 
-// Rank one digit per lane within the wave, skipping digit bits on which every
-// active lane agrees (uniform ballots need no vector work).
-__device__ __forceinline__ int wave_match_rank_skip(uint32_t d, bool valid, int *rank) {
-    const uint64_t act = __ballot(valid);
-    uint64_t same = act;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
-        if (bal != 0ull && bal != act) same &= ((d >> b) & 1u) ? bal : ~bal;
+// Rank one digit per lane within the wave among the lanes holding the same digit.
+// Only the digit bits in `vmask` can differ (the others agree across the whole
+// unit), so only those are balloted; the loop over them is wave-uniform.  Invalid
+// lanes carry digit 0 and are left out of `same` from the start.
+__device__ __forceinline__ int wave_match_rank_bits(uint32_t d, bool valid, uint32_t vmask, int *rank) {
+    uint64_t same = __ballot(valid);
+    for (uint32_t m = vmask; m; m &= m - 1u) {
+        const int b = __builtin_ctz(m);
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        same &= bit ? bal : ~bal;
     }
     *rank = __popcll(same & lanemask_lt());
     return __popcll(same);
@@ -933,18 +935,19 @@ __device__ __forceinline__ void wave_scan256(const uint32_t tot[4], uint32_t pre
     }
 }
 
-// The bucket kernel runs 512-thread workgroups: its LDS allows two workgroups
-// per CU, and the extra waves hide LDS and memory latency.
+// The bucket kernel runs 512-thread workgroups, three per CU (LDS and registers
+// allow that many), and the extra waves hide LDS and memory latency.
 constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
 
-// One stable LSD pass of the 512-thread unit sort on the 8-bit digit at `shift`.  This
-// wave's keys are cur[base_pos + k*64 + lane] for k < rounds, positions below `limit`;
-// each key goes to nxt at (keys of smaller digits) + (keys of its digit in lower waves
-// or earlier in this wave).  Keys and ranks stay in registers between the two sweeps.
+// One stable LSD pass of the 512-thread unit sort on the 8-bit digit at `shift`, of
+// which the bits in `vmask` vary in the unit.  This wave's keys are
+// cur[base_pos + k*64 + lane] for k < rounds, positions below `limit`; each key goes
+// to nxt at (keys of smaller digits) + (keys of its digit in lower waves or earlier
+// in this wave).  Keys and ranks stay in registers between the two sweeps.
 template <int W, int KB>
-__device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, int shift, int base_pos, int rounds,
-                                                int limit, uint16_t (*s_cnt)[256]) {
+__device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, int shift, uint32_t vmask,
+                                                int base_pos, int rounds, int limit, uint16_t (*s_cnt)[256]) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     constexpr int kBK = KB;
     *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = 0ull;
@@ -959,7 +962,7 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
         if (valid) kr[k] = cur[pos];
         const uint32_t d = valid ? digit_of<W>(kr[k], shift) : 0u;
         int rk;
-        const int tot = wave_match_rank_skip(d, valid, &rk);
+        const int tot = wave_match_rank_bits(d, valid, vmask, &rk);
         uint32_t base = 0;
         if (valid) base = s_cnt[w][d];
         if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
@@ -1165,11 +1168,12 @@ void bucket_kernel(BucketArgs a) {
         // digits cover only the bits that vary in this unit; a window in which no key
         // differs would be an identity pass and is skipped
         for (int shift = lo_bit; shift < nbits; shift += 8) {
-            if (digit_of<W>(orkey, shift) == 0u) continue;  // workgroup-uniform
+            const uint32_t vm = digit_of<W>(orkey, shift);  // varying bits of this window
+            if (vm == 0u) continue;                         // workgroup-uniform
             const int base_pos = first ? my0 : w * CHd;
             const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's uniques
             const int limit = first ? my0 + uw : u;
-            unit_radix_pass<W, kBK>(cur, nxt, shift, base_pos, rounds, limit, s_cnt);
+            unit_radix_pass<W, kBK>(cur, nxt, shift, vm, base_pos, rounds, limit, s_cnt);
             Key<W> *t = cur;
             cur = nxt;
             nxt = t;
@@ -1328,8 +1332,9 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
         Key<W> *cur = s_uq, *nxt = s_in;
         const int Kd = (u + kBThreads - 1) / kBThreads;
         for (int shift = lo_bit; shift < nbits; shift += 8) {
-            if (digit_of<W>(orkey, shift) == 0u) continue;
-            unit_radix_pass<W, kBK>(cur, nxt, shift, w * Kd * kWave, Kd, u, s_cnt);
+            const uint32_t vm = digit_of<W>(orkey, shift);
+            if (vm == 0u) continue;
+            unit_radix_pass<W, kBK>(cur, nxt, shift, vm, w * Kd * kWave, Kd, u, s_cnt);
             Key<W> *tmp = cur;
             cur = nxt;
             nxt = tmp;
