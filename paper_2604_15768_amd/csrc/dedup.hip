@@ -103,15 +103,16 @@ __device__ __forceinline__ int lowest_varying_bit(const uint64_t *orx) {
     return 0;
 }
 
-// Rank 64 digits of one wave: *rank = position among same-digit lanes below,
-// return = number of active lanes with the same digit.
-__device__ __forceinline__ int wave_match_rank(uint32_t d, bool valid, int *rank) {
-    const uint64_t act = __ballot(valid);
-    uint64_t same = act;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
+// Rank one digit per lane within the wave among the lanes holding the same digit.
+// Only the digit bits in `vmask` can differ (the others agree across the whole
+// unit), so only those are balloted; the loop over them is wave-uniform.  Invalid
+// lanes carry digit 0 and are left out of `same` from the start.
+__device__ __forceinline__ int wave_match_rank_bits(uint32_t d, bool valid, uint32_t vmask, int *rank) {
+    uint64_t same = __ballot(valid);
+    for (uint32_t m = vmask; m; m &= m - 1u) {
+        const int b = __builtin_ctz(m);
         const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(valid && bit);
+        const uint64_t bal = __ballot(bit);
         same &= bit ? bal : ~bal;
     }
     *rank = __popcll(same & lanemask_lt());
@@ -143,10 +144,13 @@ __device__ void radix_offsets(RadixLds &R, uint32_t *dtot) {
 // Stable LSD radix sort (8-bit digits over bits [0, nbits)) of m <= CAP keys in LDS.
 // Returns the buffer holding the result (buf or tmp).
 template <int W>
-__device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, RadixLds &R) {
+__device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, const Key<W> &orkey, RadixLds &R) {
     using C = DCfg<W>;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int shift = 0; shift < nbits; shift += 8) {
+        const uint32_t vm = digit_of<W>(orkey, shift);  // bits of this window that vary
+        if (vm == 0u) continue;                         // an identity pass
+
         for (int d = lane; d < 256; d += kWave) R.cnt[w][d] = 0;
         Key<W> kr[C::K];
         uint32_t meta[C::K];  // local rank | digit << 16
@@ -162,7 +166,7 @@ __device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, Ra
             }
             const uint32_t d = valid ? digit_of<W>(key, shift) : 0u;
             int rk;
-            const int tot = wave_match_rank(d, valid, &rk);
+            const int tot = wave_match_rank_bits(d, valid, vm, &rk);
             uint32_t base = 0;
             if (valid) base = R.cnt[w][d];
             if (valid && rk == 0) R.cnt[w][d] = base + (uint32_t)tot;
@@ -190,7 +194,7 @@ __device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, Ra
 
 // block-wide OR of (key ^ ref) over keys[0..m) read through `get`
 template <int W, typename Get>
-__device__ int block_varying_bits(int64_t m, const Key<W> &ref, Get get, RadixLds &R) {
+__device__ int block_varying_bits(int64_t m, const Key<W> &ref, Get get, RadixLds &R, Key<W> *orkey) {
     if (threadIdx.x == 0) R.orx[0] = R.orx[1] = 0;
     __syncthreads();
     uint64_t acc[W];
@@ -207,7 +211,7 @@ __device__ int block_varying_bits(int64_t m, const Key<W> &ref, Get get, RadixLd
     __syncthreads();
     uint64_t o[W];
 #pragma unroll
-    for (int j = 0; j < W; ++j) o[j] = R.orx[j];
+    for (int j = 0; j < W; ++j) orkey->w[j] = o[j] = R.orx[j];
     __syncthreads();
     return varying_bits<W>(o);
 }
@@ -221,11 +225,14 @@ __device__ int global_radix_sort(const uint64_t *X0, uint64_t *X, uint64_t *Y, i
     using C = DCfg<W>;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const Key<W> ref = load_key<W>(X0, 0);
-    const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return load_key<W>(X0, i); }, R);
+    Key<W> orkey;
+    const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return load_key<W>(X0, i); }, R, &orkey);
     const uint64_t *src = X0;
     uint64_t *dst = Y;
     int where = 0;  // 0: data in X0/X, 1: data in Y
     for (int shift = 0; shift < nbits; shift += 8) {
+        const uint32_t vm = digit_of<W>(orkey, shift);  // bits of this window that vary
+        if (vm == 0u) continue;                         // an identity pass
         // sweep 1: digit totals
         gbase[threadIdx.x] = 0;
         __syncthreads();
@@ -257,7 +264,7 @@ __device__ int global_radix_sort(const uint64_t *X0, uint64_t *X, uint64_t *Y, i
                 }
                 const uint32_t d = valid ? digit_of<W>(key, shift) : 0u;
                 int rk;
-                const int tot = wave_match_rank(d, valid, &rk);
+                const int tot = wave_match_rank_bits(d, valid, vm, &rk);
                 uint32_t base = 0;
                 if (valid) base = R.cnt[w][d];
                 if (valid && rk == 0) R.cnt[w][d] = base + (uint32_t)tot;
@@ -371,8 +378,9 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     __syncthreads();
     const Key<W> ref = s_buf[0];
     __syncthreads();
-    const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R);
-    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, (int)M, nbits, R);
+    Key<W> orkey;
+    const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R, &orkey);
+    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, (int)M, nbits, orkey, R);
     for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
         const int64_t r = ((int64_t)(j + 1) * M) / f;
         store_key<W>(sp, j, res[r]);
@@ -397,8 +405,9 @@ __global__ __launch_bounds__(kDThreads) void sample_runs_kernel(LevelArgs a, int
     __syncthreads();
     const Key<W> ref = s_buf[0];
     __syncthreads();
-    const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, R);
-    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, m, nbits, R);
+    Key<W> orkey;
+    const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, R, &orkey);
+    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, m, nbits, orkey, R);
     for (int k = threadIdx.x; k < m; k += kDThreads) store_key<W>(a.sample_buf, k0 + k, res[k]);
 }
 
@@ -894,22 +903,6 @@ __device__ __forceinline__ uint32_t key_hash(const Key<W> &k, int log_t) {
     for (int j = 1; j < W; ++j) x ^= k.w[j] * 0x9E3779B97F4A7C15ull;
     const uint32_t y = (uint32_t)x ^ (uint32_t)(x >> 32) * 0x85EBCA6Bu;
     return (y * 0x9E3779B1u) >> (32 - log_t);
-}
-
-// Rank one digit per lane within the wave among the lanes holding the same digit.
-// Only the digit bits in `vmask` can differ (the others agree across the whole
-// unit), so only those are balloted; the loop over them is wave-uniform.  Invalid
-// lanes carry digit 0 and are left out of `same` from the start.
-__device__ __forceinline__ int wave_match_rank_bits(uint32_t d, bool valid, uint32_t vmask, int *rank) {
-    uint64_t same = __ballot(valid);
-    for (uint32_t m = vmask; m; m &= m - 1u) {
-        const int b = __builtin_ctz(m);
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        same &= bit ? bal : ~bal;
-    }
-    *rank = __popcll(same & lanemask_lt());
-    return __popcll(same);
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
