@@ -1067,19 +1067,18 @@ void bucket_kernel(BucketArgs a) {
         const int Km = (m + kBThreads - 1) / kBThreads;
         const int CHm = Km * kWave;
         const int my0 = w * CHm;
-        {
-            // every load in flight before the first LDS store
-            Key<W> tmp[kBK];
+        // this lane's keys stay in registers (positions my0 + k*64 + lane, the order of
+        // the hashing and compaction below); LDS holds them for the probes' comparisons
+        Key<W> kk[kBK];
 #pragma unroll
-            for (int k = 0; k < kBK; ++k) {
-                const int i = k * kBThreads + threadIdx.x;
-                if (i < m) tmp[k] = load_key<W>(a.src, start + i);
-            }
+        for (int k = 0; k < kBK; ++k) {
+            const int i = my0 + k * kWave + lane;
+            if (k < Km && i < m) kk[k] = load_key<W>(a.src, start + i);
+        }
 #pragma unroll
-            for (int k = 0; k < kBK; ++k) {
-                const int i = k * kBThreads + threadIdx.x;
-                if (i < m) s_k0[i] = tmp[k];
-            }
+        for (int k = 0; k < kBK; ++k) {
+            const int i = my0 + k * kWave + lane;
+            if (k < Km && i < m) s_k0[i] = kk[k];
         }
         // hash table of 16-bit key indices (0xffff = empty), two slots per 32-bit word
         int log_t = 4;
@@ -1092,10 +1091,12 @@ void bucket_kernel(BucketArgs a) {
         const Key<W> ref = s_k0[0];
         // bit k of `fresh`: this lane's key of round k is the first occurrence of its value
         uint32_t fresh = 0;
-        for (int k = 0; k < Km; ++k) {
+#pragma unroll
+        for (int k = 0; k < kBK; ++k) {
+            if (k >= Km) break;  // wave-uniform
             const int i = my0 + k * kWave + lane;
             if (i >= m) continue;
-            const Key<W> key = s_k0[i];
+            const Key<W> key = kk[k];
             uint32_t h = key_hash<W>(key, log_t);
             while (true) {
                 const uint32_t cur = tab[h >> 1];
@@ -1119,12 +1120,14 @@ void bucket_kernel(BucketArgs a) {
         uint64_t acc[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) acc[j] = 0;
-        for (int k = 0; k < Km; ++k) {
+#pragma unroll
+        for (int k = 0; k < kBK; ++k) {
+            if (k >= Km) break;  // wave-uniform
             const int i = my0 + k * kWave + lane;
             const bool keep = (i < m) && ((fresh >> k) & 1u);
             Key<W> key;
             if (keep) {
-                key = s_k0[i];
+                key = kk[k];
 #pragma unroll
                 for (int j = 0; j < W; ++j) acc[j] |= key.w[j] ^ ref.w[j];
             }
