@@ -1,0 +1,82 @@
+"""Host logic of bench.py that turns counter records into reported figures (no GPU)."""
+import importlib.util
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_template_args(bench):
+    ta = bench._template_args
+    assert ta("void sci::hist_kernel<1, 4096>(sci::LevelArgs)", "hist_kernel") == ["1", "4096"]
+    assert ta("(scatter_kernel<W, C::F2>)", "scatter_kernel") == ["W", "C::F2"]
+    assert ta("void sci::bucket_kernel<2>(sci::BucketArgs)", "bucket_kernel") == ["2"]
+    assert ta("sci::scan_apply_kernel(long*, long const*)", "scan_apply_kernel") == []
+    # nested template arguments stay whole
+    assert ta("f<Key<2>, 3>(x)", "f") == ["Key<2>", "3"]
+
+
+def test_recorded_traffic_matches_instantiation(bench):
+    path = os.path.join(ROOT, "profiles", "kernel_traffic.json")
+    rec = json.load(open(path))["kernels"]
+    fams = {e["family"] for e in rec.values()}
+    assert {"gen_kernel", "bucket_kernel", "hist_kernel", "scatter_kernel", "emit_kernel"} <= fams
+    # the two levels of the partition are told apart by their fan-out argument
+    lvl1 = bench.recorded_traffic("(hist_kernel<W, C::F1>)", 1)
+    lvl2 = bench.recorded_traffic("(hist_kernel<W, C::F2>)", 1)
+    if lvl1 is not None and lvl2 is not None:
+        names = [n for n, e in rec.items() if e["family"] == "hist_kernel"]
+        by_arg = {bench._template_args(n, "hist_kernel")[1]: e for n, e in rec.items() if n in names}
+        assert lvl1 == pytest.approx(by_arg["4096"]["read_bytes"] + by_arg["4096"]["write_bytes"])
+        assert lvl2 == pytest.approx(by_arg["512"]["read_bytes"] + by_arg["512"]["write_bytes"])
+    # a kernel without a record, and a width without one, give nothing
+    assert bench.recorded_traffic("no_such_kernel<W>", 1) is None
+    assert bench.recorded_traffic("bucket_kernel<W>", 7) is None
+
+
+def test_recorded_traffic_refuses_changed_source(bench, tmp_path, monkeypatch):
+    # a record whose source hash does not match the file is not reported
+    fake_root = tmp_path
+    (fake_root / "profiles").mkdir()
+    (fake_root / "src.hip").write_text("kernel text")
+    rec = {"kernels": {"void sci::bucket_kernel<1>(sci::BucketArgs)": {
+        "family": "bucket_kernel", "source": "src.hip", "source_sha256": "0" * 64,
+        "read_bytes": 1.0, "write_bytes": 2.0}}}
+    (fake_root / "profiles" / "kernel_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "__file__", str(fake_root / "bench.py"))
+    assert bench.recorded_traffic("bucket_kernel<W>", 1) is None
+    import hashlib
+    rec["kernels"]["void sci::bucket_kernel<1>(sci::BucketArgs)"]["source_sha256"] = \
+        hashlib.sha256(b"kernel text").hexdigest()
+    (fake_root / "profiles" / "kernel_traffic.json").write_text(json.dumps(rec))
+    assert bench.recorded_traffic("bucket_kernel<W>", 1) == 3.0
+
+
+def test_gen_dedup_traffic_sums_per_step(bench, monkeypatch):
+    per_kernel = {
+        "(gen_kernel<1, true>)": {"ms_per_launch": 10.0, "launches_per_step": 1.0},
+        "scan_apply_kernel": {"ms_per_launch": 0.5, "launches_per_step": 4.0},
+        "hpsi_kernel<1>": {"ms_per_launch": 3.0, "launches_per_step": 1.0},  # energy stage: left out
+        "emit_kernel<W>": {"ms_per_launch": 5.0, "launches_per_step": 1.0},
+    }
+    table = {"(gen_kernel<1, true>)": 40e9, "scan_apply_kernel": 1e9, "emit_kernel<W>": None}
+    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W: table.get(name))
+    r = bench.gen_dedup_traffic(per_kernel, 1, 20.0, 5000.0)
+    assert r["bytes_per_step"] == pytest.approx(40e9 + 4e9)
+    assert r["achieved"] == pytest.approx(44e9 / 0.020 / 1e9)
+    assert r["frac_of_copy"] == pytest.approx(r["achieved"] / 5000.0)
+    assert r["time_covered"] == pytest.approx(12.0 / 17.0)
+    # nothing recorded: the copy rate is still reported
+    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W: None)
+    r0 = bench.gen_dedup_traffic(per_kernel, 1, 20.0, 5000.0)
+    assert r0["achieved"] is None and r0["copy_GBps"] == 5000.0 and r0["time_covered"] == 0.0
