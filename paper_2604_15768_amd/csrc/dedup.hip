@@ -592,9 +592,11 @@ __global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
 }
 
 // Scatter pass: each key to its bucket's range (order inside a bucket is free).
-// The scatter pass runs 1,024-thread workgroups, two per CU: the open output runs
+// The scatter pass runs one 1,024-thread workgroup per CU: the open output runs
 // stay one per bucket per workgroup while twice as many loads are in flight as with
-// 512 threads (level-2 scatter 16.4 -> 15.3 ms on the medium workload).
+// 512 threads (level-2 scatter 16.4 -> 15.3 ms on the medium workload), and one
+// workgroup per CU rather than two halves the partial lines held open in L2
+// (both levels together 31-34 -> 28.4 ms).
 constexpr int kSThreads = 1024;
 
 template <int W, int FMAX>
@@ -1774,10 +1776,10 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             const int64_t cbound = tiles_bound * (int64_t)a.F;
             SCI_HIP_TRY(device_scan(counts, a.cbase + S_cur, cbound, sums, scal + 2, st));
             if (lvl == 0) {
-                SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
+                SCI_LAUNCH((scatter_kernel<W, C::F1>), dim3((unsigned)std::min<int64_t>(tiles_bound, n_cu)),
                            dim3(kSThreads), 0, st, a);
             } else {
-                SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)std::min<int64_t>(tiles_bound, 2 * n_cu)),
+                SCI_LAUNCH((scatter_kernel<W, C::F2>), dim3((unsigned)std::min<int64_t>(tiles_bound, n_cu)),
                            dim3(kSThreads), 0, st, a);
             }
             const int64_t slots = (int64_t)S_cur * a.F;
