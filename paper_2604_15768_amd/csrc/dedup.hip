@@ -39,8 +39,8 @@ struct DCfg {
     static constexpr int CH = CAP / kDWaves;               // keys per wave
     static constexpr int TARGET = CAP * 3 / 8;             // mean final bucket size (tail past CAP is rare)
     static constexpr int F1 = 4096;                        // level-1 fan-out bound
-    static constexpr int F2 = (W == 1) ? 512 : 256;        // level-2 fan-out bound
-    static constexpr int OVS2 = CAP / F2;                  // level-2 oversampling (8)
+    static constexpr int F2 = 512;                         // level-2 fan-out bound
+    static constexpr int OVS2 = CAP / F2;                  // level-2 oversampling (6 W=1, 3 W=2)
     static constexpr int M1 = 65536;                       // level-1 sample bound
     static constexpr int64_t TILE1 = 131072;               // keys per level-1 tile
     static constexpr int64_t TILE2 = 16384;                // keys per level-2 tile
