@@ -37,7 +37,9 @@ struct DCfg {
     static constexpr int CAP = (W == 1) ? 3072 : 1536;     // LDS sort capacity (keys)
     static constexpr int K = CAP / kDThreads;              // keys per thread
     static constexpr int CH = CAP / kDWaves;               // keys per wave
-    static constexpr int TARGET = CAP * 3 / 8;             // mean final bucket size (tail past CAP is rare)
+    // mean final bucket size (tail past CAP is rare); two-word keys get three level-2
+    // samples per bucket, a wider spread, so their mean stays further below CAP
+    static constexpr int TARGET = (W == 1) ? CAP * 3 / 8 : CAP / 4;
     static constexpr int F1 = 4096;                        // level-1 fan-out bound
     static constexpr int F2 = 512;                         // level-2 fan-out bound
     static constexpr int OVS2 = CAP / F2;                  // level-2 oversampling (6 W=1, 3 W=2)
