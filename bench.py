@@ -45,6 +45,8 @@ def parse():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the large-workload streaming and energy/autograd timings")
+    ap.add_argument("--extras", default="select,screened,large,batch",
+                    help="comma list of the extra measurements to run (select, screened, large, batch)")
     ap.add_argument("--large-sources", type=int, default=32768)
     ap.add_argument("--large-chunk", type=int, default=0, help="pool chunk (candidates); 0: pick the fastest of 2^28..2^30")
     ap.add_argument("--batch-chunks", type=int, default=32,
@@ -590,17 +592,23 @@ def main():
         "gen_dedup_hbm": gen_dedup_traffic(per_kernel, W, g_ms + d_ms, copy_gbps),
     }
     if not args.no_extras:
-        result["extras"] = {"reverse_index_topk": select_extras(torch, sci, keys, n_cand, set_out, n_set_out,
-                                                                 n_unique, sel, n_sel, W, ws_d)}
-        result["extras"]["screened_generation"] = screened_extras(torch, sci, ham, sel, n_sel, n_cand, keys, hij,
-                                                                  g_ms)
+        want = set(args.extras.split(","))
+        result["extras"] = {}
+        if "select" in want:
+            result["extras"]["reverse_index_topk"] = select_extras(torch, sci, keys, n_cand, set_out, n_set_out,
+                                                                   n_unique, sel, n_sel, W, ws_d)
+        if "screened" in want:
+            result["extras"]["screened_generation"] = screened_extras(torch, sci, ham, sel, n_sel, n_cand, keys,
+                                                                      hij, g_ms)
         del keys, hij, set_out, ws_d
         torch.cuda.empty_cache()
-        ls, eg = large_extras(args, torch, sci, si)
-        result["extras"].update({"large_stream": ls, "energy_grad_large": eg})
-        torch.cuda.empty_cache()
-        bg, be = batch_extras(args, torch, sci, si)
-        result["extras"].update({"batched_generation": bg, "batched_energy": be})
+        if "large" in want:
+            ls, eg = large_extras(args, torch, sci, si)
+            result["extras"].update({"large_stream": ls, "energy_grad_large": eg})
+            torch.cuda.empty_cache()
+        if "batch" in want:
+            bg, be = batch_extras(args, torch, sci, si)
+            result["extras"].update({"batched_generation": bg, "batched_energy": be})
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, args.cpu_sources)
         if args.cpu_single_sources > 0:
