@@ -621,7 +621,9 @@ __global__ __launch_bounds__(kSThreads) void scatter_kernel(LevelArgs a) {
         const int64_t *cp = a.counts + a.cbase[s];
         for (int j = threadIdx.x; j < f; j += kT) s_cur[j] = (uint32_t)cp[(int64_t)j * T + t];
         __syncthreads();
-        constexpr int U = 8;
+        // sixteen keys per thread in flight: with one workgroup per CU the loads, not
+        // the stores, set the pace (levels 1+2: 31.0 -> 27.3 ms against eight)
+        constexpr int U = 16;
         for (int64_t i0 = start; i0 < end; i0 += (int64_t)U * kT) {
             Key<W> k[U];
             int b[U];
