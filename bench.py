@@ -1,32 +1,45 @@
 #!/usr/bin/env python3
 """Throughput of the NNQS-SCI hot path on one MI355X.
 
-One step = one pass of the whole path over the medium workload
-(n_orb = 26 spatial orbitals, 7 alpha + 7 beta electrons, Cholesky rank 100,
-100,000 selected determinants as one uint64 each), inputs resident in HBM:
+Headline step (default, the large workload: n_orb = 60 spatial orbitals,
+10 alpha + 10 beta electrons, Cholesky rank 240, 200,000 selected determinants
+as two uint64 words each), inputs resident in HBM:
 
-  1. sci_gen_coupled   all 2,513,700,000 coupled determinants + H_ij (FP64, dense)
-  2. sci_dedup_merge   global de-duplication of those keys, merged into S
-  3. sci_energy        E(psi) over S and dE/dpsi
+  1. sci_stream_dedup  one mini-batch of 32,768 sources of S: all their
+                       11,837,440,000 coupled determinants + H_ij (FP64, dense),
+                       generated into a two-buffer device pool in chunks of 2^30
+                       candidates and de-duplicated + merged into S chunk by chunk
+                       (generation of chunk k+1 overlaps the dedup of chunk k)
+  2. sci_energy        E(psi) over all of S and dE/dpsi
 
 Printed: one JSON line.  `value` = coupled candidates carried through the whole
-step per second.  Per-stage times come from HIP events on the stream the
-library launches on; per-kernel times come from the library's own event pairs
-around each launch (sci_profile_enable).  `roofline` describes the kernel with
-the largest share of the step, against its algorithmic bytes per launch;
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+step per second.  Stage times come from HIP events on the launching stream;
+per-kernel times come from the library's own event pairs around each launch
+(sci_profile_enable), on the stream each kernel is launched on.  `roofline`
+describes the kernel with the largest share of the step against its
+algorithmic bytes (defined per kernel below, from per-chunk set sizes measured
+in an untimed pass before the timed steps); `cpu_baseline` times the CPU oracle
+on a bounded sample of the same workload.  Extras (same line) cover the medium
+workload's full step, screened generation, the reverse index and top-K, energy
+and autograd timings, and the batched workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
+                    [--no-extras] [--extras LIST] [--no-cpu-baseline]
+    python bench.py --record-traffic FETCH_DIR WRITE_DIR WORKLOAD   (host only)
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def parse():
@@ -34,23 +47,31 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=["tiny", "medium"])
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sources", type=int, default=8000)
-    ap.add_argument("--cpu-single-sources", type=int, default=500,
-                    help="sources of the single-thread oracle sample (0: skip)")
+    ap.add_argument("--cpu-sources", type=int, default=0,
+                    help="sources of the oracle sample (0: 192 large, 8000 medium, all tiny)")
+    ap.add_argument("--cpu-single-sources", type=int, default=-1,
+                    help="sources of the single-thread oracle sample (0: skip; -1: per workload)")
+    ap.add_argument("--medium-cpu-sources", type=int, default=25000,
+                    help="sources of the oracle leg of the medium extra (0: skip)")
     ap.add_argument("--cpu-only", action="store_true",
-                    help="time only the oracle on --cpu-sources sources and print it (no GPU)")
+                    help="time only the oracle on --cpu-sources sources of --workload and print it (no GPU)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one plain device copy of this size first (counter calibration)")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the large-workload streaming and energy/autograd timings")
-    ap.add_argument("--extras", default="select,screened,large,batch",
-                    help="comma list of the extra measurements to run (select, screened, large, batch)")
+    ap.add_argument("--counters", action="store_true",
+                    help="a run for counter collection: no size pass, no extras, no CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement")
+    ap.add_argument("--extras", default="medium,select,screened,energy,batch",
+                    help="comma list of extras (medium, select, screened, energy, batch)")
     ap.add_argument("--large-sources", type=int, default=32768)
-    ap.add_argument("--large-chunk", type=int, default=0, help="pool chunk (candidates); 0: pick the fastest of 2^28..2^30")
+    ap.add_argument("--large-chunk", type=int, default=1 << 30,
+                    help="pool chunk in candidates (0: time 2^28, 2^29, 2^30 once each and keep the fastest)")
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
+    ap.add_argument("--record-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "WORKLOAD"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
+                         "profiles/kernel_traffic.json entries for WORKLOAD, then exit")
     return ap.parse_args()
 
 
@@ -65,6 +86,483 @@ def _median_ms(fn, reps, torch):
         b.synchronize()
         ts.append(a.elapsed_time(b))
     return float(np.median(ts))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# ---------------------------------------------------------------------------
+# counter records (rocprofv3 --pmc) -> calibrated HBM bytes per kernel launch
+# ---------------------------------------------------------------------------
+
+def _template_args(name, fam):
+    """Template arguments of `fam` in a kernel name, as strings ([] when not a template)."""
+    i = name.find(fam + "<")
+    if i < 0:
+        return []
+    j, depth = i + len(fam) + 1, 1
+    k = j
+    while k < len(name) and depth:
+        depth += {"<": 1, ">": -1}.get(name[k], 0)
+        k += 1
+    return [a.strip() for a in name[j:k - 1].split(",")]
+
+
+# fan-outs of the two partition levels as the compiled kernels spell them (DCfg<W>)
+FANOUT = {"C::F1": "4096", "C::F2": "512"}
+
+
+def family(name):
+    return name.strip("()").split("<")[0].split("(")[0].split("::")[-1].strip()
+
+
+def recorded_traffic(kernel_name, W, workload=None):
+    """HBM bytes per launch of `kernel_name` from the committed PMC record, or None when
+    there is none or the kernel's source file changed since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    fam = family(kernel_name)
+    want = [str(W) if a == "W" else FANOUT.get(a, a) for a in _template_args(kernel_name, fam)]
+    if "workloads" in rec:
+        tables = [rec["workloads"].get(workload, {}).get("kernels", {})] if workload else \
+            [w.get("kernels", {}) for w in rec["workloads"].values()]
+    else:
+        tables = [rec.get("kernels", {})]
+    root = os.path.dirname(path)
+    for table in tables:
+        for name, e in table.items():
+            if e.get("family") != fam or _template_args(name, fam) != want:
+                continue
+            src = os.path.join(os.path.dirname(root), e["source"])
+            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != e["source_sha256"]:
+                return None
+            return e["read_bytes"] + e["write_bytes"]
+    return None
+
+
+def _read_pmc_csv(d):
+    """{kernel name: [value per dispatch]} from the counter CSV files under d."""
+    import csv
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    out, calib = {}, []
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+            val = float(row.get("Counter_Value") or row.get("Counter-Value") or 0.0)
+            out.setdefault(name, []).append(val)
+    return out
+
+
+def record_traffic(fetch_dir, write_dir, workload):
+    """Calibrated FETCH_SIZE / WRITE_SIZE (KiB per dispatch in the CSV) per launch of every
+    library kernel of a run, stored under `workload` in profiles/kernel_traffic.json
+    with the SHA-256 of the kernel's source file.  The run includes a plain device copy
+    of --calib-copy-gib GiB (__amd_rocclr_copyBuffer): its counters against the bytes it
+    moves give the scale factors."""
+    fetch, write = _read_pmc_csv(fetch_dir), _read_pmc_csv(write_dir)
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no calibration copy in the fetch run (use --calib-copy-gib)")
+    big_f = max(fetch[copy[0]])
+    big_w = max(write[[k for k in write if "copyBuffer" in k][0]])
+    gib = max(big_f, big_w) / 2**20  # the copy moves the same bytes each way
+    moved = round(gib) * 2**30
+    read_scale, write_scale = moved / (big_f * 1024.0), moved / (big_w * 1024.0)
+    srcs = {}
+    for f in glob.glob(os.path.join(HERE, "paper_2604_15768_amd", "csrc", "*.hip")):
+        srcs[f] = open(f).read()
+    kernels = {}
+    for name, vals in fetch.items():
+        if "sci::" not in name or name not in write:
+            continue
+        fam = family(name.split("(")[0])
+        # the file that defines the kernel: "__global__ ... fam(" with no ';' or '{' between
+        pat = re.compile(r"__global__[^;{]*?\b" + re.escape(fam) + r"\s*\(", re.S)
+        src = next((p for p, t in srcs.items() if pat.search(t)), None)
+        if src is None:
+            continue
+        kernels[name] = {"family": fam, "source": os.path.relpath(src, HERE),
+                         "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+                         "launches": len(vals),
+                         "read_bytes": float(np.mean(vals)) * 1024.0 * read_scale,
+                         "write_bytes": float(np.mean(write[name])) * 1024.0 * write_scale}
+    path = os.path.join(HERE, "profiles", "kernel_traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    if "workloads" not in rec:
+        rec = {"workloads": {}}
+    rec["workloads"][workload] = {"read_scale": read_scale, "write_scale": write_scale,
+                                  "calibration": f"{round(gib)} GiB device copy", "kernels": kernels}
+    json.dump(rec, open(path, "w"), indent=1)
+    print(f"{len(kernels)} kernels recorded for {workload} (read x{read_scale:.3f}, write x{write_scale:.3f})")
+
+
+def copy_bandwidth(torch, dev, gib=4.0, reps=3):
+    """Read + write GB/s of a plain device-to-device copy of `gib` GiB (median of `reps`)."""
+    nel = int(gib * 2**30) // 8
+    a = torch.empty(nel, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nel * 8 / (float(np.median(ts)) / 1000.0) / 1e9
+
+
+def gen_dedup_traffic(per_kernel, W, stage_ms, copy_gbps, workload=None):
+    """HBM bytes the counters recorded for the generation and dedup kernels of one step
+    (PMC FETCH_SIZE + WRITE_SIZE, calibrated, per launch) over the stage time.  Kernels
+    without a current record (small ones, or source changed since the counters were
+    taken) are left out; `time_covered` is the share of kernel time that has one."""
+    tot_bytes, covered_ms, all_ms = 0.0, 0.0, 0.0
+    for name, k in per_kernel.items():
+        if "hpsi" in name or "reduce" in name or "grad" in name:
+            continue  # energy stage
+        ms = k["ms_per_launch"] * k["launches_per_step"]
+        all_ms += ms
+        b = recorded_traffic(name, W, workload)
+        if b is not None:
+            tot_bytes += b * k["launches_per_step"]
+            covered_ms += ms
+    if covered_ms == 0.0:
+        return {"bytes_per_step": None, "achieved": None, "copy_GBps": copy_gbps, "time_covered": 0.0}
+    gbps = tot_bytes / (stage_ms / 1000.0) / 1e9
+    return {"bytes_per_step": tot_bytes, "stage_ms": stage_ms, "achieved": gbps, "unit": "GB/s",
+            "frac_of_peak": gbps / HBM_PEAK_GBS, "peak": HBM_PEAK_GBS,
+            "copy_GBps": copy_gbps, "frac_of_copy": gbps / copy_gbps, "time_covered": covered_ms / all_ms}
+
+
+# ---------------------------------------------------------------------------
+# timing helpers
+# ---------------------------------------------------------------------------
+
+def timed_steps(torch, sci, step, steps, stage_names):
+    """Run `steps` steps; step(ev) records len(stage_names)+1 events on the launching
+    stream.  Returns (ms per step from the host clock, mean stage ms, per-kernel table)."""
+    n_ev = len(stage_names) + 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+    stage = [[] for _ in stage_names]
+    kern_ms, kern_calls = {}, {}
+    torch.cuda.synchronize()
+    sci.sci_profile_read()
+    sci.sci_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(ev)
+        ev[-1].synchronize()
+        for i in range(len(stage_names)):
+            stage[i].append(ev[i].elapsed_time(ev[i + 1]))
+        for name, ms in sci.sci_profile_read():
+            kern_ms[name] = kern_ms.get(name, 0.0) + ms
+            kern_calls[name] = kern_calls.get(name, 0) + 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sci.sci_profile_enable(False)
+    per_kernel = {name: {"ms_per_launch": kern_ms[name] / kern_calls[name],
+                         "launches_per_step": kern_calls[name] / steps} for name in kern_ms}
+    return 1000.0 * wall / steps, {n: float(np.mean(v)) for n, v in zip(stage_names, stage)}, per_kernel
+
+
+def roofline(per_kernel, algo_bytes_per_step, W, workload):
+    """The kernel with the largest time per step, against its algorithmic bytes.  Kernels
+    launched several times per step (one per chunk) are averaged: bytes per launch =
+    bytes per step / launches per step."""
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_launch"] * per_kernel[k]["launches_per_step"])
+    k = per_kernel[dom]
+    nb = algo_bytes_per_step(dom)
+    if nb is None:
+        return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "ms_per_launch": k["ms_per_launch"]}
+    per_launch = nb / k["launches_per_step"]
+    gbps = per_launch / (k["ms_per_launch"] / 1000.0) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbps / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, W, workload),
+            "algorithmic_bytes_per_launch": per_launch, "ms_per_launch": k["ms_per_launch"],
+            "launches_per_step": k["launches_per_step"]}
+
+
+def kernel_rates(per_kernel, algo_bytes_per_step):
+    """Algorithmic GB/s of every kernel that has a definition (fraction of HBM peak)."""
+    out = {}
+    for name, k in per_kernel.items():
+        nb = algo_bytes_per_step(name)
+        if nb is None:
+            continue
+        gbps = nb / (k["ms_per_launch"] * k["launches_per_step"] / 1000.0) / 1e9
+        out[name] = {"GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBS, 4),
+                     "ms_per_step": round(k["ms_per_launch"] * k["launches_per_step"], 3)}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# headline: one large-workload mini-batch streamed through the pool + energy
+# ---------------------------------------------------------------------------
+
+def large_chunk_sizes(torch, sci, ham, dets, sel, total, chunk):
+    """Untimed pass: the same chunks merged one by one into S with host-visible counts.
+    Per chunk: n (candidates), u (distinct keys of the chunk), m0 / m1 (set size
+    before / after).  Also the final union size, which the streamed run must equal."""
+    dev = dets.device
+    W = ham.W
+    n_sel = sel.shape[0]
+    keys = torch.empty((chunk, W), dtype=torch.int64, device=dev)
+    hij = torch.empty(chunk, dtype=torch.float64, device=dev)
+    ws = torch.empty(sci.sci_dedup_workspace_bytes(W, chunk), dtype=torch.uint8, device=dev)
+    cap = int(min(total + n_sel, 3_400_000_000))
+    set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
+    set_b = torch.empty_like(set_a)
+    set_a[:n_sel] = sel
+    n_a = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    n_b = torch.zeros(1, dtype=torch.int64, device=dev)
+    n_u = torch.zeros(1, dtype=torch.int64, device=dev)
+    flags = sci.new_flags(dev)
+    sizes = []
+    cur, nxt, n_cur, n_nxt = set_a, set_b, n_a, n_b
+    for a in range(0, total, chunk):
+        b = min(a + chunk, total)
+        sci.sci_gen_coupled(ham, dets, dets.shape[0], a, b, -1.0, keys, hij, None, chunk, None, flags)
+        # distinct keys of the chunk: a merge into nothing, count only (output in set_b's tail is
+        # not possible while it is the target, so the pool's H buffer is not used: use nxt)
+        sci.sci_dedup_merge(W, keys, b - a, None, None, nxt, n_u, cap, None, None, 0, ws, ws.numel(), flags)
+        u = int(n_u.item())
+        m0 = int(n_cur.item())
+        sci.sci_dedup_merge(W, keys, b - a, cur, n_cur, nxt, n_nxt, cap, None, None, 0, ws, ws.numel(), flags)
+        m1 = int(n_nxt.item())
+        sizes.append({"n": b - a, "u": u, "m0": m0, "m1": m1})
+        cur, nxt, n_cur, n_nxt = nxt, cur, n_nxt, n_cur
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "chunk size pass")
+    del keys, hij, ws, set_a, set_b
+    torch.cuda.empty_cache()
+    return sizes
+
+
+def large_algo(sizes, n_src, W):
+    """Algorithmic bytes per step of each kernel of the streamed mini-batch (8W-byte keys):
+      gen_kernel      every candidate's key + H_ij written, every source read once
+      hist_kernel     every candidate key read (one level)
+      scatter_kernel  every candidate key read and written (one level)
+      bucket_kernel   chunk keys read, the chunk's distinct keys written, and the running
+                      set's keys read once (the union count needs each of them compared)
+      emit_kernel     distinct chunk keys + running set read, the new set written
+    Others (splitters, scans, oversized units) have no definition here."""
+    kb = 8 * W
+    n = sum(s["n"] for s in sizes)
+    u = sum(s["u"] for s in sizes)
+    m0 = sum(s["m0"] for s in sizes)
+    m1 = sum(s["m1"] for s in sizes)
+    table = {"gen_kernel": n * (kb + 8) + n_src * kb, "hist_kernel": n * kb, "scatter_kernel": 2 * n * kb,
+             "bucket_kernel": (n + u + m0) * kb, "emit_kernel": (u + m0 + m1) * kb}
+    return lambda name: table.get(family(name))
+
+
+def large_headline(args, torch, sci, si, copy_gbps):
+    wl = si.WORKLOADS["large"]
+    sysm = si.make_system(wl)
+    dev = torch.device("cuda", 0)
+    ham = sci.Ham(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri)
+    W = ham.W
+    sel = sci.keys_to_device(sysm.dets)
+    psi = torch.from_numpy(sysm.psi).to(dev)
+    n_sel = sel.shape[0]
+    n_src = min(args.large_sources, n_sel)
+    dets = sel[:n_src]
+    total = n_src * ham.n_coupled
+    cur = torch.cuda.current_stream()
+    dd = torch.cuda.Stream()
+    out = {}
+
+    def buffers(chunk):
+        ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
+        free_bytes = torch.cuda.mem_get_info(dev)[0]
+        # the two set buffers take what HBM has left (the union is far below the candidate count)
+        cap = int(min(total + n_sel, (free_bytes - ws_bytes - (6 << 30)) // (2 * W * 8)))
+        return (torch.empty(ws_bytes, dtype=torch.uint8, device=dev),
+                torch.empty((cap, W), dtype=torch.int64, device=dev),
+                torch.empty((cap, W), dtype=torch.int64, device=dev), cap)
+
+    n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    energy = torch.zeros(1, dtype=torch.float64, device=dev)
+    hpsi = torch.empty(n_sel, dtype=torch.float64, device=dev)
+    grad = torch.empty(n_sel, dtype=torch.float64, device=dev)
+    ws_e = torch.empty(sci.sci_energy_workspace_bytes(n_sel), dtype=torch.uint8, device=dev)
+    flags = sci.new_flags(dev)
+
+    chunk = args.large_chunk
+    if chunk <= 0:  # sweep: one timed pass each after a warm-up pass
+        sweep = {}
+        for c in (1 << 28, 1 << 29, 1 << 30):
+            ws, set_a, set_b, cap = buffers(c)
+            run = lambda: (sci.sci_stream_dedup(ham, dets, n_src, 0, total, c, sel, n_in, set_a, set_b, cap, n_out,
+                                                ws, ws.numel(), flags, cur, dd), cur.wait_stream(dd))
+            run()
+            torch.cuda.synchronize()
+            sweep[c] = _median_ms(run, 1, torch)
+            del ws, set_a, set_b
+            torch.cuda.empty_cache()
+        chunk = min(sweep, key=sweep.get)
+        out["chunk_sweep_ms"] = {str(c): round(v, 1) for c, v in sweep.items()}
+
+    sizes = None if args.counters else large_chunk_sizes(torch, sci, ham, dets, sel, total, chunk)
+    torch.cuda.reset_peak_memory_stats(dev)
+    ws, set_a, set_b, cap = buffers(chunk)
+
+    def step(ev):
+        ev[0].record(cur)
+        sci.sci_stream_dedup(ham, dets, n_src, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out,
+                             ws, ws.numel(), flags, cur, dd)
+        cur.wait_stream(dd)
+        ev[1].record(cur)
+        sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, cur)
+        ev[2].record(cur)
+
+    warm = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(args.warmup):
+        step(warm)
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "bench warmup")
+    ms_step, stages, per_kernel = timed_steps(torch, sci, step, args.steps, ["stream", "energy"])
+    sci.check_flags(flags, "bench")
+    n_union = int(n_out.item())
+    peak = torch.cuda.max_memory_allocated(dev)
+    s_ms = stages["stream"]
+    kb = 8 * W
+    gen_bytes = total * (kb + 8) + n_src * kb
+    dedup_lb = 2 * total * kb
+    res = {
+        "metric": "coupled dets+H_ij/s and dedup keys/s (HBM GB/s); E+dE/dpsi time",
+        "value": total / (ms_step / 1000.0),
+        "unit": "candidates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
+                        f"one mini-batch of the first {n_src} sources ({total} candidates) streamed through the "
+                        f"device pool in chunks of {chunk} into S (sci_stream_dedup) + E and dE/dpsi over S",
+            "n_candidates": total, "n_unique_union": n_union, "chunk": chunk,
+            "n_chunks": -(-total // chunk),
+            "stage_ms": {"gen_dedup_stream": s_ms, "energy_grad": stages["energy"]},
+            "candidates_per_s_stream": total / (s_ms / 1000.0),
+            "energy": float(energy.item()),
+            "device_bytes": {"pool_and_workspace": ws.numel(), "set_buffers": 2 * cap * kb, "peak_allocated": peak},
+        },
+        "kernels": per_kernel,
+    }
+    if sizes is not None:
+        assert sizes[-1]["m1"] == n_union, "streamed union differs from the chunk-by-chunk merges"
+        algo = large_algo(sizes, n_src, W)
+        res["roofline"] = roofline(per_kernel, algo, W, "large")
+        res["kernel_rates"] = kernel_rates(per_kernel, algo)
+        res["config"]["chunk_sizes"] = sizes
+        res["gen_dedup_algorithmic"] = {
+            "bytes_per_step": gen_bytes + dedup_lb, "stage_ms": s_ms,
+            "achieved": (gen_bytes + dedup_lb) / (s_ms / 1000.0) / 1e9, "unit": "GB/s",
+            "frac_of_peak": (gen_bytes + dedup_lb) / (s_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+            "definition": "generation (keys + H_ij written, sources read) + dedup lower bound "
+                          "(every candidate key read once and written once), over the stream stage time"}
+        res["gen_dedup_hbm"] = gen_dedup_traffic(per_kernel, W, s_ms, copy_gbps, "large")
+    res.update(out)
+    del ws, set_a, set_b
+    torch.cuda.empty_cache()
+    return res, (ham, sel, psi, sysm)
+
+
+# ---------------------------------------------------------------------------
+# extras
+# ---------------------------------------------------------------------------
+
+def medium_step(args, torch, sci, si, copy_gbps):
+    """The medium workload's whole step (all 100,000 sources): generation of every coupled
+    determinant (2.51e9, dense, one launch), dedup-merge into S, energy + gradient."""
+    wl = si.WORKLOADS["medium"]
+    sysm = si.make_system(wl)
+    dev = torch.device("cuda", 0)
+    ham = sci.Ham(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri)
+    n_sel = sysm.dets.shape[0]
+    n_cand = n_sel * ham.n_coupled
+    W = ham.W
+    sel = sci.keys_to_device(sysm.dets)
+    psi = torch.from_numpy(sysm.psi).to(dev)
+    keys = torch.empty((n_cand, W), dtype=torch.int64, device=dev)
+    hij = torch.empty(n_cand, dtype=torch.float64, device=dev)
+    set_cap = n_cand + n_sel
+    n_set_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    set_out = torch.empty((set_cap, W), dtype=torch.int64, device=dev)
+    n_set_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_d = torch.empty(sci.sci_dedup_workspace_bytes(W, n_cand), dtype=torch.uint8, device=dev)
+    ws_e = torch.empty(sci.sci_energy_workspace_bytes(n_sel), dtype=torch.uint8, device=dev)
+    energy = torch.zeros(1, dtype=torch.float64, device=dev)
+    hpsi = torch.empty(n_sel, dtype=torch.float64, device=dev)
+    grad = torch.empty(n_sel, dtype=torch.float64, device=dev)
+    flags = sci.new_flags(dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        ev[0].record(stream)
+        sci.sci_gen_coupled(ham, sel, n_sel, 0, n_cand, -1.0, keys, hij, None, n_cand, None, flags, stream)
+        ev[1].record(stream)
+        sci.sci_dedup_merge(W, keys, n_cand, sel, n_set_in, set_out, n_set_out, set_cap, None, None, 0,
+                            ws_d, ws_d.numel(), flags, stream)
+        ev[2].record(stream)
+        sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, stream)
+        ev[3].record(stream)
+
+    warm = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):
+        step(warm)
+    torch.cuda.synchronize()
+    sci.check_flags(flags, "medium warmup")
+    # distinct candidate keys (a merge into nothing, untimed): the bucket kernel's output size
+    n_zero = torch.zeros(1, dtype=torch.int64, device=dev)
+    sci.sci_dedup_merge(W, keys, n_cand, None, None, set_out, n_zero, set_cap, None, None, 0, ws_d, ws_d.numel(),
+                        flags, stream)
+    torch.cuda.synchronize()
+    n_distinct = int(n_zero.item())
+    step(warm)  # the union again (set_out was used above)
+    torch.cuda.synchronize()
+    n_union = int(n_set_out.item())
+    ms_step, st, per_kernel = timed_steps(torch, sci, step, 10, ["gen", "dedup", "energy"])
+    sci.check_flags(flags, "medium")
+    kb = 8 * W
+    gen_bytes = n_cand * (kb + 8) + n_sel * kb
+    dedup_lb = 2 * n_cand * kb
+    table = {"gen_kernel": gen_bytes, "hist_kernel": n_cand * kb, "scatter_kernel": 2 * n_cand * kb,
+             "bucket_kernel": (n_cand + n_distinct + n_sel) * kb, "emit_kernel": (n_distinct + n_sel + n_union) * kb}
+    algo = lambda name: table.get(family(name))
+    res = {
+        "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
+                    f"full generation (one launch) + dedup-merge into S + E and dE/dpsi",
+        "n_candidates": n_cand, "n_distinct_candidates": n_distinct, "n_unique_union": n_union,
+        "ms_per_step": ms_step, "candidates_per_s": n_cand / (ms_step / 1000.0), "stage_ms": st,
+        "gen_candidates_per_s": n_cand / (st["gen"] / 1000.0), "dedup_keys_per_s": n_cand / (st["dedup"] / 1000.0),
+        "roofline": roofline(per_kernel, algo, W, "medium"),
+        "kernel_rates": kernel_rates(per_kernel, algo),
+        "gen_dedup_algorithmic": {
+            "bytes_per_step": gen_bytes + dedup_lb, "achieved": (gen_bytes + dedup_lb) / ((st["gen"] + st["dedup"]) / 1000.0) / 1e9,
+            "frac_of_peak": (gen_bytes + dedup_lb) / ((st["gen"] + st["dedup"]) / 1000.0) / 1e9 / HBM_PEAK_GBS},
+        "gen_dedup_hbm": gen_dedup_traffic(per_kernel, W, st["gen"] + st["dedup"], copy_gbps, "medium"),
+        "energy": float(energy.item()),
+        "kernels": per_kernel,
+    }
+    ctx = dict(ham=ham, sel=sel, n_sel=n_sel, keys=keys, hij=hij, n_cand=n_cand, set_out=set_out,
+               n_set_out=n_set_out, n_union=n_union, ws_d=ws_d, gen_ms=st["gen"], sysm=sysm)
+    return res, ctx
 
 
 def screened_extras(torch, sci, ham, sel, n_sel, n_cand, keys, hij, dense_ms):
@@ -145,6 +643,23 @@ def select_extras(torch, sci, keys, n_cand, union, n_union_dev, n_union, sel, n_
     t_ms = _median_ms(run, 3, torch)
     out["topk"] = {"n": nn, "k": K, "ms": t_ms, "entries_per_s": nn / (t_ms / 1000.0), "n_selected": int(n_out.item())}
     return out
+
+
+def energy_extras(torch, sci, ham, sel, psi):
+    """E and E + dE/dpsi over all of the large S: the plain entry point and the autograd path
+    (forward + backward, which recomputes H psi)."""
+    n_sel = sel.shape[0]
+    e_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=False), 5, torch)
+    eg_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=True), 5, torch)
+
+    def auto():
+        p = psi.clone().requires_grad_(True)
+        e = sci.SciEnergy.apply(p, ham, sel)
+        e.backward()
+
+    ag_ms = _median_ms(auto, 5, torch)
+    return {"workload": f"large: E over all {n_sel} selected determinants", "n_sel": n_sel,
+            "energy_ms": e_ms, "energy_grad_ms": eg_ms, "autograd_fwd_bwd_ms": ag_ms}
 
 
 def batch_extras(args, torch, sci, si):
@@ -246,171 +761,20 @@ def batch_extras(args, torch, sci, si):
     return gen, en
 
 
-def large_extras(args, torch, sci, si):
-    """Large workload (n_orb=60, 10a+10b, W=2): one mini-batch of `large_sources` sources
-    of S (32768 by default, over 1e10 candidates) streamed through the device pool
-    (generation of chunk k+1 overlapping dedup-merge of chunk k into S), and E / E+dE/dpsi
-    over all of S, plain and through autograd."""
-    wl = si.WORKLOADS["large"]
-    sysm = si.make_system(wl)
-    dev = torch.device("cuda", 0)
-    ham = sci.Ham(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri)
-    sel = sci.keys_to_device(sysm.dets)
-    n_sel = sel.shape[0]
-    n_src = min(args.large_sources, n_sel)
-    dets = sel[:n_src]
-    total = n_src * ham.n_coupled
-    chunks = [args.large_chunk] if args.large_chunk > 0 else [1 << 28, 1 << 29, 1 << 30]
-    W = ham.W
-    ws_bytes = max(sci.sci_stream_workspace_bytes(ham, c) for c in chunks)
-    # the two set buffers take what HBM has left (the union is far below the candidate count)
-    free_bytes = torch.cuda.mem_get_info(dev)[0]
-    cap = int(min(total + n_sel, (free_bytes - ws_bytes - (8 << 30)) // (2 * W * 8)))
-    set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
-    set_b = torch.empty_like(set_a)
-    n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
-    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    flags = sci.new_flags(dev)
-    gen_stream = torch.cuda.current_stream()
-    dd_stream = torch.cuda.Stream()
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands on a bounded sample
+# ---------------------------------------------------------------------------
 
-    def run_chunk(c):
-        sci.sci_stream_dedup(ham, dets, n_src, 0, total, c, sel, n_in, set_a, set_b, cap, n_out,
-                             ws, ws.numel(), flags, gen_stream, dd_stream)
-        torch.cuda.current_stream().wait_stream(dd_stream)
-
-    # pool chunk: the fastest of the candidates, one timed pass each after a warm-up pass
-    torch.cuda.reset_peak_memory_stats(dev)
-    sweep = {}
-    for c in chunks:
-        run_chunk(c)
-        torch.cuda.synchronize()
-        sci.check_flags(flags, "large stream warmup")
-        sweep[c] = _median_ms(lambda: run_chunk(c), 1, torch)
-    peak_alloc = torch.cuda.max_memory_allocated(dev)
-    chunk = min(sweep, key=sweep.get)
-    run = lambda: run_chunk(chunk)
-    sci.sci_profile_read()
-    sci.sci_profile_enable(True)
-    t_ms = _median_ms(run, 3, torch)
-    torch.cuda.synchronize()
-    kern = {}
-    for name, ms in sci.sci_profile_read():
-        kern[name] = kern.get(name, 0.0) + ms / 3
-    sci.sci_profile_enable(False)
-    sci.check_flags(flags, "large stream")
-    n_union = int(n_out.item())
-    del set_a, set_b, ws
-    out = {
-        "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
-                    f"one mini-batch of the first {n_src} sources streamed in pool chunks of {chunk} candidates, merged into S",
-        "n_candidates": total, "n_unique_union": n_union, "ms": t_ms,
-        "chunk": chunk, "chunk_sweep_ms": {str(c): round(v, 1) for c, v in sweep.items()},
-        "device_bytes": {"pool_and_workspace": ws_bytes, "set_buffers": 2 * cap * W * 8,
-                         "peak_allocated": peak_alloc},
-        "candidates_per_s": total / (t_ms / 1000.0),
-        "kernel_ms": {k: round(v, 3) for k, v in sorted(kern.items(), key=lambda x: -x[1]) if v >= 0.05},
-    }
-    # energy and gradient over the large S: plain entry point and the autograd path
-    psi = torch.from_numpy(sysm.psi).to(dev)
-    e_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=False), 5, torch)
-    eg_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=True), 5, torch)
-
-    def auto():
-        p = psi.clone().requires_grad_(True)
-        e = sci.SciEnergy.apply(p, ham, sel)
-        e.backward()
-
-    ag_ms = _median_ms(auto, 5, torch)
-    energy = {"workload": f"{wl.name}: E over all {n_sel} selected determinants", "n_sel": n_sel,
-              "energy_ms": e_ms, "energy_grad_ms": eg_ms, "autograd_fwd_bwd_ms": ag_ms}
-    return out, energy
-
-
-def _template_args(name, fam):
-    """Template arguments of `fam` in a kernel name, as strings ([] when not a template)."""
-    i = name.find(fam + "<")
-    if i < 0:
-        return []
-    j, depth = i + len(fam) + 1, 1
-    k = j
-    while k < len(name) and depth:
-        depth += {"<": 1, ">": -1}.get(name[k], 0)
-        k += 1
-    return [a.strip() for a in name[j:k - 1].split(",")]
-
-
-def recorded_traffic(kernel_name, W):
-    """HBM bytes per launch of `kernel_name` from the committed PMC record, or None when
-    there is none or the kernel's source file changed since the counters were taken."""
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "kernel_traffic.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    fam = kernel_name.strip("()").split("<")[0]
-    # the label's template arguments as the compiled kernel spells them
-    fan = {"C::F1": "4096", "C::F2": "512" if W == 1 else "256"}
-    want = [str(W) if a == "W" else fan.get(a, a) for a in _template_args(kernel_name, fam)]
-    for name, e in rec.get("kernels", {}).items():
-        if e.get("family") != fam or _template_args(name, fam) != want:
-            continue
-        src = os.path.join(here, e["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != e["source_sha256"]:
-            return None
-        return e["read_bytes"] + e["write_bytes"]
-    return None
-
-
-def copy_bandwidth(torch, dev, gib=4.0, reps=3):
-    """Read + write GB/s of a plain device-to-device copy of `gib` GiB (median of `reps`)."""
-    nel = int(gib * 2**30) // 8
-    a = torch.empty(nel, dtype=torch.int64, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    ts = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    del a, b
-    torch.cuda.empty_cache()
-    return 2 * nel * 8 / (float(np.median(ts)) / 1000.0) / 1e9
-
-
-def gen_dedup_traffic(per_kernel, W, stage_ms, copy_gbps):
-    """HBM bytes the counters recorded for the generation and dedup kernels of one step
-    (PMC FETCH_SIZE + WRITE_SIZE, calibrated, per launch) over the two stages' time.
-    Kernels without a current record (small ones, or source changed since the counters
-    were taken) are left out; `time_covered` is the share of kernel time that has one."""
-    tot_bytes, covered_ms, all_ms = 0.0, 0.0, 0.0
-    for name, k in per_kernel.items():
-        if "hpsi" in name or "reduce" in name or "grad" in name:
-            continue  # energy stage
-        ms = k["ms_per_launch"] * k["launches_per_step"]
-        all_ms += ms
-        b = recorded_traffic(name, W)
-        if b is not None:
-            tot_bytes += b * k["launches_per_step"]
-            covered_ms += ms
-    if covered_ms == 0.0:
-        return {"bytes_per_step": None, "achieved": None, "copy_GBps": copy_gbps, "time_covered": 0.0}
-    gbps = tot_bytes / (stage_ms / 1000.0) / 1e9
-    return {"bytes_per_step": tot_bytes, "stage_ms": stage_ms, "achieved": gbps, "unit": "GB/s",
-            "frac_of_peak": gbps / HBM_PEAK_GBS, "peak": HBM_PEAK_GBS,
-            "copy_GBps": copy_gbps, "frac_of_copy": gbps / copy_gbps, "time_covered": covered_ms / all_ms}
+DEFAULT_CPU_SOURCES = {"large": 192, "medium": 8000, "tiny": 200}
+DEFAULT_SINGLE_SOURCES = {"large": 16, "medium": 500, "tiny": 200}
 
 
 def cpu_baseline(sysm, n_src):
-    """The oracle, as it stands, on the first n_src sources: generation,
-    dedup of their candidates into S, and H psi for the same rows."""
+    """The oracle, as it stands, on the first n_src sources: generation, dedup of their
+    candidates into S, and H psi for the same rows (enumeration + search in S)."""
     import oracle
     wl = sysm.workload
+    n_src = min(n_src, sysm.dets.shape[0])
     dets = sysm.dets[:n_src]
     t0 = time.perf_counter()
     keys, _, _ = oracle.gen_coupled(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri, dets)
@@ -420,17 +784,19 @@ def cpu_baseline(sysm, n_src):
     dt = time.perf_counter() - t0
     n_cand = keys.shape[0]
     return {"value": n_cand / dt, "unit": "candidates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n_src} of {dets.shape[0] if n_src > dets.shape[0] else sysm.dets.shape[0]} "
-                      f"sources: generation ({n_cand} candidates), dedup into S, H psi rows; {dt:.1f} s"}
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{wl.name}: first {n_src} of {sysm.dets.shape[0]} sources: generation ({n_cand} candidates), "
+                      f"dedup into S, H psi rows; {dt:.1f} s"}
 
 
-def single_thread_baseline(n_src):
+def single_thread_baseline(workload, n_src):
     """The oracle on one host thread, timed in a child process (OpenMP fixes its thread
     count when the library loads); the child runs only the CPU oracle."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--cpu-sources", str(n_src)]
-    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", workload,
+           "--cpu-sources", str(n_src)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
         return {"error": r.stderr[-300:]}
     return json.loads(r.stdout.strip().splitlines()[-1])
@@ -438,45 +804,23 @@ def single_thread_baseline(n_src):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
         sys.exit(2)
+    import sci_inputs as si
     if args.cpu_only:
-        import sci_inputs as si
-        print(json.dumps(cpu_baseline(si.make_system(si.WORKLOADS[args.workload]), args.cpu_sources)), flush=True)
+        n = args.cpu_sources or DEFAULT_CPU_SOURCES[args.workload]
+        print(json.dumps(cpu_baseline(si.make_system(si.WORKLOADS[args.workload]), n)), flush=True)
         return
     import torch
 
     import paper_2604_15768_amd as sci
-    import sci_inputs as si
 
-    wl = si.WORKLOADS[args.workload]
-    sysm = si.make_system(wl)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    ham = sci.Ham(wl.n_orb, wl.n_alpha, wl.n_beta, sysm.h1, sysm.eri)
-    n_sel = sysm.dets.shape[0]
-    n_cand = n_sel * ham.n_coupled
-    W = ham.W
-
-    # resident inputs and preallocated outputs / workspaces
-    sel = sci.keys_to_device(sysm.dets)
-    psi = torch.from_numpy(sysm.psi).to(dev)
-    keys = torch.empty((n_cand, W), dtype=torch.int64, device=dev)
-    hij = torch.empty(n_cand, dtype=torch.float64, device=dev)
-    n_gen = torch.zeros(1, dtype=torch.int64, device=dev)
-    set_cap = n_cand + n_sel
-    n_set_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
-    set_out = torch.empty((set_cap, W), dtype=torch.int64, device=dev)
-    n_set_out = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws_d = torch.empty(sci.sci_dedup_workspace_bytes(W, n_cand), dtype=torch.uint8, device=dev)
-    ws_e = torch.empty(sci.sci_energy_workspace_bytes(n_sel), dtype=torch.uint8, device=dev)
-    energy = torch.zeros(1, dtype=torch.float64, device=dev)
-    hpsi = torch.empty(n_sel, dtype=torch.float64, device=dev)
-    grad = torch.empty(n_sel, dtype=torch.float64, device=dev)
-    flags = sci.new_flags(dev)
-    stream = torch.cuda.current_stream()
-
     if args.calib_copy_gib > 0:
         nel = int(args.calib_copy_gib * 2**30) // 8
         a = torch.empty(nel, dtype=torch.int64, device=dev)
@@ -484,135 +828,58 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-
+        torch.cuda.empty_cache()
     # bandwidth a plain device copy reaches here (read + write), the practical ceiling
     copy_gbps = copy_bandwidth(torch, dev)
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-
-    def step(record=False):
-        if record:
-            ev[0].record(stream)
-        sci.sci_gen_coupled(ham, sel, n_sel, 0, n_cand, -1.0, keys, hij, None, n_cand, n_gen, flags, stream)
-        if record:
-            ev[1].record(stream)
-        sci.sci_dedup_merge(W, keys, n_cand, sel, n_set_in, set_out, n_set_out, set_cap, None, None, 0,
-                            ws_d, ws_d.numel(), flags, stream)
-        if record:
-            ev[2].record(stream)
-        sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, stream)
-        if record:
-            ev[3].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    sci.check_flags(flags, "bench warmup")
-    n_unique = int(n_set_out.item())
-
-    t_gen, t_dd, t_en = [], [], []
-    kern_ms, kern_calls = {}, {}
-    torch.cuda.synchronize()
-    sci.sci_profile_read()
-    sci.sci_profile_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(record=True)
-        ev[3].synchronize()
-        t_gen.append(ev[0].elapsed_time(ev[1]))
-        t_dd.append(ev[1].elapsed_time(ev[2]))
-        t_en.append(ev[2].elapsed_time(ev[3]))
-        for name, ms in sci.sci_profile_read():
-            kern_ms[name] = kern_ms.get(name, 0.0) + ms
-            kern_calls[name] = kern_calls.get(name, 0) + 1
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sci.sci_profile_enable(False)
-    sci.check_flags(flags, "bench")
-    ms_step = 1000.0 * wall / args.steps
-
-    g_ms = float(np.mean(t_gen))
-    d_ms = float(np.mean(t_dd))
-    e_ms = float(np.mean(t_en))
-    gen_bytes = n_cand * (8 * W + 8) + n_sel * 8 * W       # written keys + H_ij, read sources
-    dedup_lb_bytes = 2 * n_cand * 8 * W                    # any sort reads and writes every key once
-    # algorithmic bytes per launch of each kernel family (what the work must move at least)
-    algo = {
-        "gen_kernel": ("hbm", gen_bytes),
-        "bucket_kernel": ("hbm", (n_cand + n_unique) * 8 * W),
-        "emit_kernel": ("hbm", 2 * n_unique * 8 * W),
-        "scatter_kernel": ("hbm", 2 * n_cand * 8 * W),
-        "hist_kernel": ("hbm", n_cand * 8 * W),
-        "merge_kernel": ("hbm", (n_unique + n_sel + n_unique) * 8 * W),
-        "merge_union_kernel": ("hbm", (n_unique + n_sel + n_unique) * 8 * W),
-    }
-    per_kernel = {}
-    for name, tot in kern_ms.items():
-        per_kernel[name] = {"ms_per_launch": tot / kern_calls[name], "launches_per_step": kern_calls[name] / args.steps}
-    dom = max(kern_ms, key=lambda k: kern_ms[k])
-    fam = next((f for f in algo if f in dom), None)
-    dom_ms = kern_ms[dom] / kern_calls[dom]
-    if fam is not None:
-        bound, nbytes = algo[fam]
-        roof = {"kernel": dom, "bound": bound, "achieved": nbytes / (dom_ms / 1000.0) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": nbytes / (dom_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
-                "traffic": recorded_traffic(dom, W),
-                "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": dom_ms}
+    extras = set() if (args.no_extras or args.counters) else set(args.extras.split(","))
+    ctx_large = None
+    if args.workload == "large":
+        result, ctx_large = large_headline(args, torch, sci, si, copy_gbps)
+        head_sysm = ctx_large[3]
     else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "ms_per_launch": dom_ms}
-    result = {
-        "metric": "coupled dets+H_ij/s and dedup keys/s (HBM GB/s); E+dE/dpsi time",
-        "value": n_cand / (ms_step / 1000.0),
-        "unit": "candidates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} "
-                        f"n_sel={n_sel} W={W}; full generation + dedup-merge into S + energy",
-            "n_candidates": n_cand,
-            "n_unique_union": n_unique,
-            "stage_ms": {"gen_coupled": g_ms, "dedup_merge": d_ms, "energy_grad": e_ms},
-            "gen_candidates_per_s": n_cand / (g_ms / 1000.0),
-            "dedup_keys_per_s": n_cand / (d_ms / 1000.0),
-            "dedup_lower_bound_GBps": dedup_lb_bytes / (d_ms / 1000.0) / 1e9,
-            "energy": float(energy.item()),
-        },
-        "roofline": roof,
-        "kernels": per_kernel,
-        "gen_roofline": {"bound": "hbm", "achieved": gen_bytes / (g_ms / 1000.0) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": gen_bytes / (g_ms / 1000.0) / 1e9 / HBM_PEAK_GBS},
-        "gen_dedup_hbm": gen_dedup_traffic(per_kernel, W, g_ms + d_ms, copy_gbps),
-    }
-    if not args.no_extras:
-        want = set(args.extras.split(","))
-        result["extras"] = {}
-        if "select" in want:
-            result["extras"]["reverse_index_topk"] = select_extras(torch, sci, keys, n_cand, set_out, n_set_out,
-                                                                   n_unique, sel, n_sel, W, ws_d)
-        if "screened" in want:
-            result["extras"]["screened_generation"] = screened_extras(torch, sci, ham, sel, n_sel, n_cand, keys,
-                                                                      hij, g_ms)
-        del keys, hij, set_out, ws_d
+        m, ctx = medium_step(args, torch, sci, si, copy_gbps) if args.workload == "medium" else (None, None)
+        if m is None:
+            raise SystemExit("--workload tiny is for --cpu-only")
+        result = {"metric": "coupled dets+H_ij/s and dedup keys/s (HBM GB/s); E+dE/dpsi time",
+                  "value": m["candidates_per_s"], "unit": "candidates/s", "n_gpus": 1, "steps": 10, "warmup": 2,
+                  "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                  "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                  "config": {"workload": m["workload"], "n_candidates": m["n_candidates"]},
+                  "roofline": m["roofline"], "medium": m}
+        head_sysm = ctx["sysm"]
+        extras.discard("medium")
+    result["copy_GBps"] = copy_gbps
+    result["extras"] = {}
+    if "energy" in extras and ctx_large is not None:
+        ham, sel, psi, _ = ctx_large
+        result["extras"]["energy_grad_large"] = energy_extras(torch, sci, ham, sel, psi)
+    ctx_large = None
+    torch.cuda.empty_cache()
+    if extras & {"medium", "select", "screened"}:
+        m, ctx = medium_step(args, torch, sci, si, copy_gbps)
+        result["extras"]["medium_step"] = m
+        if "select" in extras:
+            result["extras"]["reverse_index_topk"] = select_extras(
+                torch, sci, ctx["keys"], ctx["n_cand"], ctx["set_out"], ctx["n_set_out"], ctx["n_union"],
+                ctx["sel"], ctx["n_sel"], ctx["ham"].W, ctx["ws_d"])
+        if "screened" in extras:
+            result["extras"]["screened_generation"] = screened_extras(
+                torch, sci, ctx["ham"], ctx["sel"], ctx["n_sel"], ctx["n_cand"], ctx["keys"], ctx["hij"],
+                ctx["gen_ms"])
+        if args.medium_cpu_sources > 0 and not args.no_cpu_baseline:
+            m["cpu_baseline"] = cpu_baseline(ctx["sysm"], args.medium_cpu_sources)
+        ctx = None
         torch.cuda.empty_cache()
-        if "large" in want:
-            ls, eg = large_extras(args, torch, sci, si)
-            result["extras"].update({"large_stream": ls, "energy_grad_large": eg})
-            torch.cuda.empty_cache()
-        if "batch" in want:
-            bg, be = batch_extras(args, torch, sci, si)
-            result["extras"].update({"batched_generation": bg, "batched_energy": be})
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(sysm, args.cpu_sources)
-        if args.cpu_single_sources > 0:
-            result["cpu_baseline"]["single_thread"] = single_thread_baseline(args.cpu_single_sources)
+    if "batch" in extras:
+        bg, be = batch_extras(args, torch, sci, si)
+        result["extras"].update({"batched_generation": bg, "batched_energy": be})
+    if not args.no_cpu_baseline and not args.counters:
+        n = args.cpu_sources or DEFAULT_CPU_SOURCES[args.workload]
+        result["cpu_baseline"] = cpu_baseline(head_sysm, n)
+        n1 = args.cpu_single_sources if args.cpu_single_sources >= 0 else DEFAULT_SINGLE_SOURCES[args.workload]
+        if n1 > 0:
+            result["cpu_baseline"]["single_thread"] = single_thread_baseline(args.workload, n1)
     print(json.dumps(result), flush=True)
 
 

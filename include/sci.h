@@ -26,7 +26,9 @@
  *   host can see are reported before anything is enqueued; the thread-local
  *   text of the last error is available from sci_last_error().  Conditions
  *   only the device can see set bits in *dev_flags (a caller-owned device
- *   uint32 that the library only ORs into; the caller clears it).
+ *   uint32 that the library only ORs into; the caller clears it).  No C++
+ *   exception leaves any entry point: a failed host allocation inside the
+ *   library is returned as SCI_ENOMEM.
  */
 #ifndef SCI_H
 #define SCI_H
@@ -79,11 +81,18 @@ int64_t sci_n_coupled(int32_t n_orb, int32_t n_alpha, int32_t n_beta);
  * Upload a Hamiltonian and build the device tables the kernels read
  * (paper section 4.2, the single/double excitation tables; here the
  * integral slices V_pq[a][b] = (ap|bq) and their antisymmetrised same-spin
- * form).  h1_host, eri_host: host arrays as above.  On success *out owns
- * about 2*n_orb^4*8 bytes of device memory until sci_ham_destroy.  The handle
- * is immutable and may be used from several streams at once.  Synchronous.
+ * form).  h1_host, eri_host: host arrays as above.  On success *out owns one
+ * device allocation of about (3*n_orb^4 + 2*n_orb^3 + 3*n_orb^2)*8 bytes
+ * (the ERI, the two n^4 slice tables, the n^3 Coulomb/exchange row tables,
+ * h1, J, K; plus small pair lists) until sci_ham_destroy: 311 MB for n_orb=60.
+ * The handle is immutable and may be used from several streams at once.
+ * Synchronous and stream-free (unlike the compute calls): the integrals are
+ * copied with blocking copies, the tables are built on the null stream, and
+ * the call returns once that stream has finished, so the handle is ready for
+ * any stream.  The host arrays may be freed on return.
  * Errors: SCI_EINVAL (null pointers, n_alpha/n_beta outside [0, n_orb]),
- * SCI_EUNSUPPORTED (n_orb > SCI_MAX_ORB), SCI_ENOMEM, SCI_EHIP.
+ * SCI_EUNSUPPORTED (n_orb > SCI_MAX_ORB), SCI_ENOMEM (device or host
+ * allocation), SCI_EHIP.
  */
 int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta,
                        const double *h1_host, const double *eri_host, sci_ham_t *out);

@@ -120,7 +120,44 @@ def _ptr(t):
         return None
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+# Host-side shape / dtype checks before raw pointers reach the kernels: a wrong
+# dtype, a strided view or a short buffer would otherwise be read past its end.
+
+def _need(cond, msg):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_keys(t, W, rows, name, device=None):
+    """t: contiguous int64 device tensor holding at least `rows` keys of W words."""
+    if t is None:
+        _need(rows == 0, f"{name}: missing")
+        return
+    _need(t.is_cuda, f"{name}: expected a device tensor")
+    _need(t.dtype == torch.int64, f"{name}: expected int64 key words, got {t.dtype}")
+    _need(t.is_contiguous(), f"{name}: expected a contiguous tensor")
+    if t.dim() == 2:
+        _need(t.shape[1] == W, f"{name}: keys have {t.shape[1]} words, the call needs W={W}")
+    _need(t.numel() >= rows * W, f"{name}: holds {t.numel() // max(W, 1)} keys, the call needs {rows}")
+    if device is not None:
+        _need(t.device == device, f"{name}: on {t.device}, expected {device}")
+
+
+def _check_vec(t, dtype, n, name, device=None):
+    """t: contiguous device tensor of `dtype` with at least n elements (None allowed when n == 0)."""
+    if t is None:
+        return
+    _need(t.is_cuda, f"{name}: expected a device tensor")
+    _need(t.dtype == dtype, f"{name}: expected {dtype}, got {t.dtype}")
+    _need(t.is_contiguous(), f"{name}: expected a contiguous tensor")
+    _need(t.numel() >= n, f"{name}: has {t.numel()} elements, the call needs {n}")
+    if device is not None:
+        _need(t.device == device, f"{name}: on {t.device}, expected {device}")
 
 
 def _stream(stream=None):
@@ -201,6 +238,16 @@ def sci_ham_destroy(ham: Ham) -> None:
 
 def sci_gen_coupled(ham: Ham, dets, n_dets, exc_begin, exc_end, eps, out_keys, out_hij, out_src,
                     capacity, n_out, dev_flags, stream=None):
+    dev = dets.device if dets is not None else None
+    _check_keys(dets, ham.W, n_dets, "dets")
+    count = max(0, exc_end - exc_begin)
+    # dense mode writes exactly `count` slots; screened mode up to min(capacity, count)
+    slots = count if eps < 0 else min(capacity, count)
+    _check_keys(out_keys, ham.W, slots, "out_keys", dev)
+    _check_vec(out_hij, torch.float64, slots, "out_hij", dev)
+    _check_vec(out_src, torch.int32, slots, "out_src", dev)
+    _check_vec(n_out, torch.int64, 1, "n_out", dev)
+    _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
     _check(_lib.sci_gen_coupled(ham.handle, _ptr(dets), n_dets, exc_begin, exc_end, float(eps),
                                 _ptr(out_keys), _ptr(out_hij), _ptr(out_src), capacity, _ptr(n_out),
                                 _ptr(dev_flags), _stream(stream)), "sci_gen_coupled")
@@ -208,6 +255,18 @@ def sci_gen_coupled(ham: Ham, dets, n_dets, exc_begin, exc_end, eps, out_keys, o
 
 def sci_dedup_merge(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity,
                     novel, n_novel, novel_capacity, workspace, workspace_bytes, dev_flags, stream=None):
+    dev = set_out.device if set_out is not None else None
+    _check_keys(cand, n_words, n_cand, "cand", dev)
+    if set_in is not None:
+        _check_keys(set_in, n_words, 0, "set_in", dev)
+        _check_vec(n_set_in, torch.int64, 1, "n_set_in", dev)
+    _check_keys(set_out, n_words, set_capacity, "set_out", dev)
+    _check_vec(n_set_out, torch.int64, 1, "n_set_out", dev)
+    if novel is not None:
+        _check_keys(novel, n_words, novel_capacity, "novel", dev)
+        _check_vec(n_novel, torch.int64, 1, "n_novel", dev)
+    _check_vec(workspace, torch.uint8, workspace_bytes, "workspace", dev)
+    _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
     _check(_lib.sci_dedup_merge(n_words, _ptr(cand), n_cand, _ptr(set_in), _ptr(n_set_in), _ptr(set_out),
                                 _ptr(n_set_out), set_capacity, _ptr(novel), _ptr(n_novel), novel_capacity,
                                 _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)),
@@ -216,6 +275,14 @@ def sci_dedup_merge(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out,
 
 def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, workspace_bytes, dev_flags,
                stream=None):
+    dev = sel.device
+    _check_keys(sel, ham.W, n_sel, "sel")
+    _check_vec(psi, torch.float64, n_sel, "psi", dev)
+    _check_vec(energy, torch.float64, 1, "energy", dev)
+    _check_vec(h_psi, torch.float64, n_sel, "h_psi", dev)
+    _check_vec(grad, torch.float64, n_sel, "grad", dev)
+    _check_vec(workspace, torch.uint8, workspace_bytes, "workspace", dev)
+    _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
     _check(_lib.sci_energy(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
                            _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_energy")
 
@@ -228,6 +295,16 @@ def sci_stream_dedup(ham: Ham, dets, n_dets, exc_begin, exc_end, chunk, set_in, 
                      set_capacity, n_set_out, workspace, workspace_bytes, dev_flags, gen_stream=None,
                      dedup_stream=None) -> bool:
     """Returns True when the final set is set_b."""
+    dev = set_a.device
+    _check_keys(dets, ham.W, n_dets, "dets", dev)
+    if set_in is not None:
+        _check_keys(set_in, ham.W, 0, "set_in", dev)
+        _check_vec(n_set_in, torch.int64, 1, "n_set_in", dev)
+    _check_keys(set_a, ham.W, set_capacity, "set_a", dev)
+    _check_keys(set_b, ham.W, set_capacity, "set_b", dev)
+    _check_vec(n_set_out, torch.int64, 1, "n_set_out", dev)
+    _check_vec(workspace, torch.uint8, workspace_bytes, "workspace", dev)
+    _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
     fb = _i32(0)
     _check(_lib.sci_stream_dedup(ham.handle, _ptr(dets), n_dets, exc_begin, exc_end, chunk, _ptr(set_in),
                                  _ptr(n_set_in), _ptr(set_a), _ptr(set_b), set_capacity, _ptr(n_set_out),
@@ -266,6 +343,7 @@ def check_flags(flags: torch.Tensor, where: str, allow=0):
 def gen_coupled(ham: Ham, dets: torch.Tensor, exc_begin=0, exc_end=None, eps=-1.0, with_src=False,
                 capacity=None, flags=None):
     """Dense (eps<0) or screened coupled generation; returns (keys, hij, src, n_out tensor)."""
+    _need(dets.dim() == 2, "dets: expected an (n, W) tensor")
     n = dets.shape[0]
     if exc_end is None:
         exc_end = n * ham.n_coupled
@@ -287,6 +365,7 @@ def gen_coupled(ham: Ham, dets: torch.Tensor, exc_begin=0, exc_end=None, eps=-1.
 def dedup_merge(cand: torch.Tensor, set_in: torch.Tensor, n_words: int, want_novel=False, set_capacity=None,
                 flags=None, workspace=None):
     """sorted(set(cand) | set(set_in)) and optionally sorted(set(cand) - set(set_in)), on the device."""
+    _need(cand.dim() == 2 and set_in.dim() == 2, "cand, set_in: expected (n, W) tensors")
     dev = cand.device
     n_cand = cand.shape[0]
     n_set = set_in.shape[0]
@@ -309,6 +388,8 @@ def dedup_merge(cand: torch.Tensor, set_in: torch.Tensor, n_words: int, want_nov
 
 def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_grad=True, flags=None,
            workspace=None):
+    _need(sel.dim() == 2 and psi.dim() == 1 and psi.shape[0] == sel.shape[0],
+          "energy: expected sel (n, W) and psi (n,)")
     dev = sel.device
     n = sel.shape[0]
     e = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -325,7 +406,12 @@ def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_
 
 def stream_dedup(ham: Ham, dets: torch.Tensor, chunk: int, set_in: torch.Tensor, set_capacity: int,
                  exc_begin=0, exc_end=None, gen_stream=None, dedup_stream=None, flags=None):
-    """Streamed generation + dedup-merge of all coupled determinants of `dets` into `set_in`."""
+    """Streamed generation + dedup-merge of all coupled determinants of `dets` into `set_in`.
+
+    The work runs on gen_stream / dedup_stream (default: the current stream); on return
+    the current stream waits for both, and every tensor the enqueued work touches is
+    recorded on the streams that use it, so the caching allocator reuses none of them
+    before that work is done.  The results may be read on the current stream."""
     dev = dets.device
     n = dets.shape[0]
     if exc_end is None:
@@ -338,8 +424,21 @@ def stream_dedup(ham: Ham, dets: torch.Tensor, chunk: int, set_in: torch.Tensor,
     ws = torch.empty(max(sci_stream_workspace_bytes(ham, chunk), 1), dtype=torch.uint8, device=dev)
     if flags is None:
         flags = new_flags(dev)
+    cur = torch.cuda.current_stream(dev)
+    gs = gen_stream if gen_stream is not None else cur
+    ds = dedup_stream if dedup_stream is not None else cur
+    # inputs written on the current stream (n_in, the flags) are ready before either stream starts
+    for s_ in (gs, ds):
+        if s_ != cur:
+            s_.wait_stream(cur)
     is_b = sci_stream_dedup(ham, dets, n, exc_begin, exc_end, chunk, set_in, n_in, set_a, set_b, set_capacity, n_out,
-                            ws, ws.numel(), flags, gen_stream, dedup_stream)
+                            ws, ws.numel(), flags, gs, ds)
+    for s_ in (gs, ds):
+        if s_ != cur:
+            cur.wait_stream(s_)
+            for t in (dets, set_in, n_in, set_a, set_b, n_out, ws, flags):
+                if t is not None:
+                    t.record_stream(s_)
     return (set_b if is_b else set_a), n_out, flags
 
 
@@ -497,6 +596,9 @@ class SciEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, psi, ham, sel):
         e, _, _, flags = energy(ham, sel, psi.detach(), want_hpsi=False, want_grad=False)
+        # a selected set that is unsorted or holds malformed determinants has no energy:
+        # raise instead of returning a number (this reads the flags, one host sync)
+        check_flags(flags, "SciEnergy.forward")
         ctx.ham = ham
         ctx.save_for_backward(psi, sel)
         return e[0]

@@ -14,6 +14,7 @@
 // Row sums run in ascending j, block sums in a fixed tree, so repeated calls
 // are bit-identical.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "sci_internal.hpp"
@@ -370,37 +371,18 @@ constexpr int kColSplit = 8;  // column blocks per row block (more workgroups in
 
 static int col_split(int64_t n_sel) { return n_sel >= (int64_t)kColSplit * kColTile ? kColSplit : 1; }
 
-static size_t energy_ws(int64_t n_sel) {
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16) +
-           al((size_t)col_split(n_sel) * n_sel * 8);
+constexpr size_t al256c(size_t b) { return (b + 255) / 256 * 256; }
+
+// workspace layout of one energy call: H psi (when the caller keeps none), per-block
+// partial sums, the two scalars, the column-block partial row sums
+constexpr size_t energy_ws(int64_t n_sel) {
+    return al256c((size_t)n_sel * 8) +
+           al256c((size_t)(n_sel > (int64_t)kRedThreads * 8 ? (n_sel + kRedThreads * 8 - 1) / (kRedThreads * 8) : 1) * 16) +
+           al256c(16) + al256c((size_t)(n_sel >= (int64_t)kColSplit * kColTile ? kColSplit : 1) * (size_t)n_sel * 8);
 }
 
-}  // namespace sci
-
-using namespace sci;
-
-extern "C" size_t sci_energy_workspace_bytes(int64_t n_sel) {
-    if (n_sel < 0) return 0;
-    return energy_ws(n_sel);
-}
-
-extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
-                              double *energy, double *h_psi, double *grad, void *workspace,
-                              size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
-    set_error("");
-    if (!ham) return fail(SCI_EINVAL, "sci_energy: NULL handle");
-    if (n_sel < 1) return fail(SCI_EINVAL, "sci_energy: n_sel must be >= 1");
-    if (!sel || !psi || !energy || !dev_flags || !workspace)
-        return fail(SCI_EINVAL, "sci_energy: NULL pointer argument");
-    if (workspace_bytes < energy_ws(n_sel))
-        return fail(SCI_ECAPACITY, "sci_energy: workspace %zu < %zu bytes", workspace_bytes, energy_ws(n_sel));
-    const HamDev &d = ham->dev;
-    if (d.W > SCI_MAX_WORDS) return fail(SCI_EUNSUPPORTED, "sci_energy: W=%d", d.W);
-    hipStream_t st = (hipStream_t)stream;
-
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    char *ws = (char *)workspace;
+static EnergyArgs energy_args(const HamDev &d, const uint64_t *sel, int64_t n_sel, const double *psi, double *energy,
+                              double *h_psi, double *grad, char *ws, uint32_t *dev_flags) {
     EnergyArgs a;
     a.n = d.n_orb;
     a.na = d.n_alpha;
@@ -417,33 +399,80 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
     a.n_sel = n_sel;
     a.psi = psi;
     a.hpsi = h_psi ? h_psi : (double *)ws;
-    a.partial = (double *)(ws + al((size_t)n_sel * 8));
-    a.scalars = (double *)(ws + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16));
-    a.partial_rows = (double *)(ws + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16));
+    const size_t o1 = al256c((size_t)n_sel * 8);
+    const size_t o2 = o1 + al256c((size_t)reduce_blocks(n_sel) * 16);
+    a.partial = (double *)(ws + o1);
+    a.scalars = (double *)(ws + o2);
+    a.partial_rows = (double *)(ws + o2 + al256c(16));
     a.energy = energy;
     a.grad = grad;
     a.flags = dev_flags;
+    return a;
+}
 
+// Every kernel of one energy evaluation, in order, on `st`.  `timed` launches go through
+// the per-launch profiler (which may create events); the allocation-free entry point
+// launches untimed.
+static int32_t energy_launch(int W, const EnergyArgs &a, hipStream_t st, bool timed) {
+#define SCI_ELAUNCH(kern, ...)                          \
+    do {                                                \
+        if (timed) SCI_LAUNCH(kern, __VA_ARGS__);       \
+        else hipLaunchKernelGGL(kern, __VA_ARGS__);     \
+    } while (0)
+    const int64_t n_sel = a.n_sel;
     const int64_t row_blocks = ceil_div(n_sel, kRowThreads);
     const int nc = col_split(n_sel);
-    if (d.W == 1) {
-        SCI_LAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
-        SCI_LAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+    if (W == 1) {
+        SCI_ELAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+        SCI_ELAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
     } else {
-        SCI_LAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
-        SCI_LAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+        SCI_ELAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+        SCI_ELAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
     }
     SCI_HIP_TRY(hipGetLastError());
     const int64_t nb = reduce_blocks(n_sel);
-    SCI_LAUNCH(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);
+    SCI_ELAUNCH(reduce_partial_kernel, dim3((unsigned)nb), dim3(kRedThreads), 0, st, a);
     SCI_HIP_TRY(hipGetLastError());
-    SCI_LAUNCH(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, st, a, (int)nb);
+    SCI_ELAUNCH(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, st, a, (int)nb);
     SCI_HIP_TRY(hipGetLastError());
-    if (grad) {
-        SCI_LAUNCH(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
+    if (a.grad) {
+        SCI_ELAUNCH(grad_kernel, dim3((unsigned)ceil_div(n_sel, 256)), dim3(256), 0, st, a);
         SCI_HIP_TRY(hipGetLastError());
     }
+#undef SCI_ELAUNCH
     return SCI_OK;
+}
+
+// argument checks shared by the energy entry points (everything but the workspace)
+static int32_t energy_check(const char *where, sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                            const double *energy, const uint32_t *dev_flags) {
+    if (!ham) return fail(SCI_EINVAL, "%s: NULL handle", where);
+    if (n_sel < 1) return fail(SCI_EINVAL, "%s: n_sel must be >= 1", where);
+    if (!sel || !psi || !energy || !dev_flags) return fail(SCI_EINVAL, "%s: NULL pointer argument", where);
+    if (ham->dev.W > SCI_MAX_WORDS) return fail(SCI_EUNSUPPORTED, "%s: W=%d", where, ham->dev.W);
+    return SCI_OK;
+}
+
+}  // namespace sci
+
+using namespace sci;
+
+extern "C" size_t sci_energy_workspace_bytes(int64_t n_sel) {
+    if (n_sel < 0) return 0;
+    return energy_ws(n_sel);
+}
+
+extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                              double *energy, double *h_psi, double *grad, void *workspace,
+                              size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
+    set_error("");
+    int32_t rc = energy_check("sci_energy", ham, sel, n_sel, psi, energy, dev_flags);
+    if (rc != SCI_OK) return rc;
+    if (!workspace) return fail(SCI_EINVAL, "sci_energy: NULL pointer argument");
+    if (workspace_bytes < energy_ws(n_sel))
+        return fail(SCI_ECAPACITY, "sci_energy: workspace %zu < %zu bytes", workspace_bytes, energy_ws(n_sel));
+    const EnergyArgs a = energy_args(ham->dev, sel, n_sel, psi, energy, h_psi, grad, (char *)workspace, dev_flags);
+    return energy_launch(ham->dev.W, a, (hipStream_t)stream, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,14 +548,23 @@ extern "C" int32_t sci_energy_batch_destroy(sci_energy_batch_t b) {
     return SCI_OK;
 }
 
+static int32_t energy_batch_create_impl(const sci_energy_item *items, int32_t n_items, uint32_t *dev_flags,
+                                        sci_energy_batch_t *out);
+
 extern "C" int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t n_items, uint32_t *dev_flags,
                                            sci_energy_batch_t *out) {
     set_error("");
+    return guarded("sci_energy_batch_create", [&] { return energy_batch_create_impl(items, n_items, dev_flags, out); });
+}
+
+// Host vectors are built before anything is allocated on the device, so a throw
+// from them leaves nothing behind.
+static int32_t energy_batch_create_impl(const sci_energy_item *items, int32_t n_items, uint32_t *dev_flags,
+                                        sci_energy_batch_t *out) {
     if (!out) return fail(SCI_EINVAL, "sci_energy_batch_create: NULL output handle");
     *out = nullptr;
     if (n_items < 1 || !items) return fail(SCI_EINVAL, "sci_energy_batch_create: empty item list");
     if (!dev_flags) return fail(SCI_EINVAL, "sci_energy_batch_create: dev_flags is NULL");
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     std::vector<EnergyArgs> args((size_t)n_items);
     std::vector<int32_t> ncol((size_t)n_items), nblk((size_t)n_items);
     std::vector<size_t> ws_off((size_t)n_items);
@@ -556,7 +594,8 @@ extern "C" int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t
     for (int w = 0; w < 2; ++w) tiles.insert(tiles.end(), rows[w].begin(), rows[w].end());
     tiles.insert(tiles.end(), red.begin(), red.end());
 
-    sci_energy_batch_s *b = new sci_energy_batch_s;
+    sci_energy_batch_s *b = new (std::nothrow) sci_energy_batch_s;
+    if (!b) return fail(SCI_ENOMEM, "sci_energy_batch_create: host allocation failed");
     b->n_items = n_items;
     b->n_hpsi[0] = (int64_t)hp[0].size();
     b->n_hpsi[1] = (int64_t)hp[1].size();
@@ -577,29 +616,8 @@ extern "C" int32_t sci_energy_batch_create(const sci_energy_item *items, int32_t
         const sci_energy_item &it = items[i];
         const HamDev &d = it.ham->dev;
         const int64_t n_sel = it.n_sel;
-        char *w = b->d_ws + ws_off[(size_t)i];
-        EnergyArgs &a = args[(size_t)i];
-        a.n = d.n_orb;
-        a.na = d.n_alpha;
-        a.nb = d.n_beta;
-        a.h1 = d.h1;
-        a.eri = d.eri;
-        a.vdir = d.vdir;
-        a.vanti = d.vanti;
-        a.jmat = d.jmat;
-        a.kmat = d.kmat;
-        a.jtpq = d.jtpq;
-        a.ktpq = d.ktpq;
-        a.sel = it.sel;
-        a.n_sel = n_sel;
-        a.psi = it.psi;
-        a.hpsi = it.h_psi ? it.h_psi : (double *)w;
-        a.partial = (double *)(w + al((size_t)n_sel * 8));
-        a.scalars = (double *)(w + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16));
-        a.partial_rows = (double *)(w + al((size_t)n_sel * 8) + al((size_t)reduce_blocks(n_sel) * 16) + al(16));
-        a.energy = it.energy;
-        a.grad = it.grad;
-        a.flags = dev_flags;
+        args[(size_t)i] = energy_args(d, it.sel, n_sel, it.psi, it.energy, it.h_psi, it.grad,
+                                      b->d_ws + ws_off[(size_t)i], dev_flags);
     }
     if (hipMemcpy(b->d_items, args.data(), args.size() * sizeof(EnergyArgs), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_ncol, ncol.data(), ncol.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||

@@ -554,11 +554,12 @@ extern "C" int32_t sci_gen_coupled(sci_ham_t ham, const uint64_t *dets, int64_t 
     if (d.W > SCI_MAX_WORDS) return fail(SCI_EUNSUPPORTED, "sci_gen_coupled: W=%d", d.W);
     if (d.n_coupled >= (1ll << 24))
         return fail(SCI_EUNSUPPORTED, "sci_gen_coupled: %lld excitations per source", (long long)d.n_coupled);
+    if (exc_end > exc_begin && (!dets || !out_keys || !out_hij))
+        return fail(SCI_EINVAL, "sci_gen_coupled: NULL buffer");
     hipStream_t st = (hipStream_t)stream;
     // n_out: dense count is known here; screened count starts at zero
     if (n_out) SCI_HIP_TRY(launch_set_i64(n_out, dense ? exc_end - exc_begin : 0, st));
     if (exc_end == exc_begin) return SCI_OK;
-    if (!dets || !out_keys || !out_hij) return fail(SCI_EINVAL, "sci_gen_coupled: NULL buffer");
 
     GenArgs a = make_gen_args(d, dets, exc_begin, exc_end, out_keys, out_hij, out_src, capacity,
                               (unsigned long long *)n_out, dev_flags, eps);
@@ -611,20 +612,24 @@ static void build_tiles(const std::vector<GenArgs> &items, int W, int64_t tile_c
 }
 
 static int32_t upload_tiles(sci_gen_batch_s *b, int64_t tile_cand) {
+    // host lists first (these may throw); the batch changes only once they exist
     std::vector<GenTile> tiles, t2;
     build_tiles(b->items, 1, tile_cand, tiles);
     build_tiles(b->items, 2, tile_cand, t2);
-    b->n_tiles[0] = (int64_t)tiles.size();
-    b->n_tiles[1] = (int64_t)t2.size();
+    const int64_t n1 = (int64_t)tiles.size(), n2 = (int64_t)t2.size();
     tiles.insert(tiles.end(), t2.begin(), t2.end());
     const int64_t nt = (int64_t)tiles.size();
     if (nt > b->tile_alloc) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
         b->d_tiles = nullptr;
+        b->tile_alloc = 0;
+        b->n_tiles[0] = b->n_tiles[1] = 0;
         SCI_HIP_TRY(hipMalloc((void **)&b->d_tiles, (size_t)std::max<int64_t>(nt, 1) * sizeof(GenTile)));
         b->tile_alloc = std::max<int64_t>(nt, 1);
     }
     if (nt) SCI_HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), (size_t)nt * sizeof(GenTile), hipMemcpyHostToDevice));
+    b->n_tiles[0] = n1;
+    b->n_tiles[1] = n2;
     b->tile_candidates = tile_cand;
     return SCI_OK;
 }
@@ -656,9 +661,18 @@ extern "C" int32_t sci_gen_batch_destroy(sci_gen_batch_t b) {
     return SCI_OK;
 }
 
+static int32_t gen_batch_create_impl(const sci_gen_item *items, int32_t n_items, int64_t tile_candidates,
+                                     uint32_t *dev_flags, sci_gen_batch_t *out);
+
 extern "C" int32_t sci_gen_batch_create(const sci_gen_item *items, int32_t n_items, int64_t tile_candidates,
                                         uint32_t *dev_flags, sci_gen_batch_t *out) {
     set_error("");
+    return guarded("sci_gen_batch_create",
+                   [&] { return gen_batch_create_impl(items, n_items, tile_candidates, dev_flags, out); });
+}
+
+static int32_t gen_batch_create_impl(const sci_gen_item *items, int32_t n_items, int64_t tile_candidates,
+                                     uint32_t *dev_flags, sci_gen_batch_t *out) {
     if (!out) return fail(SCI_EINVAL, "sci_gen_batch_create: NULL output handle");
     *out = nullptr;
     if (n_items < 0 || (n_items > 0 && !items)) return fail(SCI_EINVAL, "sci_gen_batch_create: bad item list");
@@ -681,7 +695,8 @@ extern "C" int32_t sci_gen_batch_create(const sci_gen_item *items, int32_t n_ite
         args.push_back(make_gen_args(d, it.dets, it.exc_begin, it.exc_end, it.out_keys, it.out_hij, nullptr,
                                      it.exc_end - it.exc_begin, nullptr, dev_flags, -1.0));
     }
-    sci_gen_batch_s *b = new sci_gen_batch_s;
+    sci_gen_batch_s *b = new (std::nothrow) sci_gen_batch_s;
+    if (!b) return fail(SCI_ENOMEM, "sci_gen_batch_create: host allocation failed");
     b->items = std::move(args);
     auto bail = [&](int32_t st) {
         sci_gen_batch_destroy(b);
@@ -693,7 +708,12 @@ extern "C" int32_t sci_gen_batch_create(const sci_gen_item *items, int32_t n_ite
     if (!b->items.empty() &&
         hipMemcpy(b->d_items, b->items.data(), b->items.size() * sizeof(GenArgs), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(SCI_EHIP, "sci_gen_batch_create: upload failed"));
-    const int32_t st = upload_tiles(b, tile_candidates);
+    int32_t st;
+    try {
+        st = upload_tiles(b, tile_candidates);
+    } catch (...) {
+        return bail(fail(SCI_ENOMEM, "sci_gen_batch_create: host allocation failed"));
+    }
     if (st != SCI_OK) return bail(st);
     int dev = 0, n_cu = 256, per1 = 1, per2 = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -715,17 +735,29 @@ extern "C" int32_t sci_gen_coupled_batched(sci_gen_batch_t batch, sci_stream_t s
     return launch_batch(batch, (hipStream_t)stream);
 }
 
+static int32_t gen_batch_autotune_impl(sci_gen_batch_t batch, sci_stream_t stream, int64_t *tile_candidates);
+
 extern "C" int32_t sci_gen_batch_autotune(sci_gen_batch_t batch, sci_stream_t stream, int64_t *tile_candidates) {
     set_error("");
+    return guarded("sci_gen_batch_autotune", [&] { return gen_batch_autotune_impl(batch, stream, tile_candidates); });
+}
+
+// The tile list is rebuilt for each size tried (host vectors: a throw leaves the
+// batch with its previous, still valid, tile list; the events are released by RAII).
+static int32_t gen_batch_autotune_impl(sci_gen_batch_t batch, sci_stream_t stream, int64_t *tile_candidates) {
     if (!batch) return fail(SCI_EINVAL, "sci_gen_batch_autotune: NULL handle");
     hipStream_t st = (hipStream_t)stream;
     static const int64_t kTry[] = {1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    SCI_HIP_TRY(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return fail(SCI_EHIP, "sci_gen_batch_autotune: event creation failed");
-    }
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    SCI_HIP_TRY(hipEventCreate(&ev.e0));
+    SCI_HIP_TRY(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int64_t best = batch->tile_candidates;
     float best_ms = -1.0f;
     int32_t rc = SCI_OK;
@@ -745,8 +777,6 @@ extern "C" int32_t sci_gen_batch_autotune(sci_gen_batch_t batch, sci_stream_t st
             best = tc;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != SCI_OK) return rc;
     if ((rc = upload_tiles(batch, best)) != SCI_OK) return rc;
     if (tile_candidates) *tile_candidates = best;

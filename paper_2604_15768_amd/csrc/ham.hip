@@ -79,24 +79,37 @@ std::vector<ProfRec> g_prof;      // records of the current window
 std::vector<hipEvent_t> g_events; // pool of created events
 size_t g_next_event = 0;
 
-hipEvent_t take_event() {
+// An event from the pool (nullptr when none can be had: that launch goes untimed).
+hipEvent_t take_event() noexcept {
     if (g_next_event == g_events.size()) {
         hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        g_events.push_back(e);
+        try {
+            g_events.push_back(e);
+        } catch (...) {
+            (void)hipEventDestroy(e);
+            return nullptr;
+        }
     }
     return g_events[g_next_event++];
 }
 }  // namespace
 
+// Timing is best effort: when the record cannot grow, the launch goes untimed and
+// nothing is thrown (this runs inside every entry point that launches a kernel).
 ProfScope::ProfScope(const char *name, hipStream_t s) : st(s), slot(-1) {
     if (!g_prof_on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     ProfRec r{name, take_event(), take_event()};
     if (!r.a || !r.b) return;
+    try {
+        g_prof.reserve(g_prof.size() + 1);
+    } catch (...) {
+        return;
+    }
     if (hipEventRecord(r.a, st) != hipSuccess) return;
     slot = (int)g_prof.size();
-    g_prof.push_back(r);
+    g_prof.push_back(r);  // capacity reserved above: cannot throw
 }
 
 ProfScope::~ProfScope() {
@@ -155,9 +168,17 @@ int64_t sci_n_coupled(int32_t n_orb, int32_t n_alpha, int32_t n_beta) {
            comb2(n_beta) * comb2(vb) + (int64_t)n_alpha * va * n_beta * vb;
 }
 
+static int32_t ham_create_impl(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const double *h1_host,
+                               const double *eri_host, sci_ham_t *out);
+
 int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const double *h1_host,
                        const double *eri_host, sci_ham_t *out) {
     set_error("");
+    return guarded("sci_ham_create", [&] { return ham_create_impl(n_orb, n_alpha, n_beta, h1_host, eri_host, out); });
+}
+
+static int32_t ham_create_impl(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const double *h1_host,
+                               const double *eri_host, sci_ham_t *out) {
     if (!out) return fail(SCI_EINVAL, "sci_ham_create: out is NULL");
     *out = nullptr;
     if (!h1_host || !eri_host) return fail(SCI_EINVAL, "sci_ham_create: NULL integrals");
@@ -187,22 +208,33 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
     }
     const int64_t total = cursor;
 
+    // pair tables on the host first: if their allocation throws, nothing is held yet
+    std::vector<uint16_t> tabs[4];
+    for (int t = 0; t < 4; ++t) {
+        const int m = pair_m[t];
+        tabs[t].reserve((size_t)std::max<int64_t>(0, comb2(m)));
+        for (int i = 0; i < m; ++i)
+            for (int j = i + 1; j < m; ++j) tabs[t].push_back((uint16_t)(i | (j << 8)));
+    }
+    sci_ham_s *h = new (std::nothrow) sci_ham_s;
+    if (!h) return fail(SCI_ENOMEM, "sci_ham_create: host allocation failed");
+
     void *block = nullptr;
-    if (hipMalloc(&block, (size_t)total) != hipSuccess)
+    if (hipMalloc(&block, (size_t)total) != hipSuccess) {
+        delete h;
         return fail(SCI_ENOMEM, "sci_ham_create: hipMalloc(%lld) failed", (long long)total);
+    }
     char *base = (char *)block;
     auto cleanup = [&](int32_t st) {
         (void)hipFree(block);
+        delete h;
         return st;
     };
     if (hipMemcpy(base + off_h1, h1_host, (size_t)(n2 * 8), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + off_eri, eri_host, (size_t)(n4 * 8), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(SCI_EHIP, "sci_ham_create: upload failed"));
     for (int t = 0; t < 4; ++t) {
-        const int m = pair_m[t];
-        std::vector<uint16_t> tab;
-        for (int i = 0; i < m; ++i)
-            for (int j = i + 1; j < m; ++j) tab.push_back((uint16_t)(i | (j << 8)));
+        const std::vector<uint16_t> &tab = tabs[t];
         if (!tab.empty() &&
             hipMemcpy(base + off_pairs[t], tab.data(), tab.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(SCI_EHIP, "sci_ham_create: pair table upload failed"));
@@ -214,11 +246,9 @@ int32_t sci_ham_create(int32_t n_orb, int32_t n_alpha, int32_t n_beta, const dou
                        (const double *)(base + off_eri), (double *)(base + off_vdir),
                        (double *)(base + off_vanti), (double *)(base + off_j),
                        (double *)(base + off_k), (double *)(base + off_jt), (double *)(base + off_kt), (int)n);
-    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
         return cleanup(fail(SCI_EHIP, "sci_ham_create: table build failed"));
 
-    sci_ham_s *h = new (std::nothrow) sci_ham_s;
-    if (!h) return cleanup(fail(SCI_ENOMEM, "sci_ham_create: host allocation failed"));
     HamDev &d = h->dev;
     d.n_orb = n_orb;
     d.n_alpha = n_alpha;

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <new>
+#include <stdexcept>
 #include <string>
 
 #include "sci.h"
@@ -69,6 +71,23 @@ struct ProfScope {
 // thread-local last-error text
 void set_error(const char *fmt, ...);
 int32_t fail(int32_t status, const char *fmt, ...);
+
+// Runs the body of a C entry point that allocates host memory: no C++ exception
+// crosses the C ABI.  An exhausted or oversized host allocation (std::bad_alloc,
+// std::length_error) and anything else thrown become SCI_ENOMEM with the entry
+// point's name in the last-error text.  The body cleans up what it owns (RAII).
+template <typename F>
+int32_t guarded(const char *where, F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(SCI_ENOMEM, "%s: host allocation failed", where);
+    } catch (const std::length_error &) {
+        return fail(SCI_ENOMEM, "%s: host allocation too large", where);
+    } catch (...) {
+        return fail(SCI_ENOMEM, "%s: unexpected host exception", where);
+    }
+}
 
 #define SCI_HIP_TRY(expr)                                                                  \
     do {                                                                                   \

@@ -95,6 +95,34 @@ def test_argument_errors_before_device():
     assert lib.sci_ham_destroy(None) == sci.SCI_OK
 
 
+def _overcommit_mode():
+    try:
+        return int(open("/proc/sys/vm/overcommit_memory").read().strip())
+    except (OSError, ValueError):
+        return None
+
+
+def test_host_allocation_failure_maps_to_enomem():
+    """A host allocation inside the library that cannot be satisfied comes back as
+    SCI_ENOMEM with a message, never as a C++ exception through the C ABI (which
+    would abort the Python process here).  A batch of 2^31 - 1 items asks for about
+    480 GB of host item records before any item is read; with heuristic overcommit
+    that allocation is refused."""
+    sci, lib = _lib()
+    if _overcommit_mode() == 1:
+        pytest.skip("the kernel grants every allocation (vm.overcommit_memory = 1)")
+    item = sci.SciGenItem()  # ham NULL: only read if the allocation were granted
+    h = ctypes.c_void_p()
+    rc = lib.sci_gen_batch_create(ctypes.byref(item), 2**31 - 1, 1 << 18, ctypes.c_void_p(0x1000), ctypes.byref(h))
+    assert rc == sci.SCI_ENOMEM, lib.sci_last_error().decode()
+    assert "sci_gen_batch_create" in lib.sci_last_error().decode()
+    assert not h.value
+    # the library keeps working afterwards
+    assert lib.sci_gen_batch_create(ctypes.byref(item), 1, 1 << 18, ctypes.c_void_p(0x1000),
+                                    ctypes.byref(h)) == sci.SCI_EINVAL
+    assert "no handle" in lib.sci_last_error().decode()
+
+
 def test_product_path_does_not_import_oracle():
     pkg = os.path.join(ROOT, "paper_2604_15768_amd")
     for dirpath, _, files in os.walk(pkg):

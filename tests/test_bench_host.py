@@ -70,13 +70,13 @@ def test_gen_dedup_traffic_sums_per_step(bench, monkeypatch):
         "emit_kernel<W>": {"ms_per_launch": 5.0, "launches_per_step": 1.0},
     }
     table = {"(gen_kernel<1, true>)": 40e9, "scan_apply_kernel": 1e9, "emit_kernel<W>": None}
-    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W: table.get(name))
+    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W, *rest: table.get(name))
     r = bench.gen_dedup_traffic(per_kernel, 1, 20.0, 5000.0)
     assert r["bytes_per_step"] == pytest.approx(40e9 + 4e9)
     assert r["achieved"] == pytest.approx(44e9 / 0.020 / 1e9)
     assert r["frac_of_copy"] == pytest.approx(r["achieved"] / 5000.0)
     assert r["time_covered"] == pytest.approx(12.0 / 17.0)
     # nothing recorded: the copy rate is still reported
-    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W: None)
+    monkeypatch.setattr(bench, "recorded_traffic", lambda name, W, *rest: None)
     r0 = bench.gen_dedup_traffic(per_kernel, 1, 20.0, 5000.0)
     assert r0["achieved"] is None and r0["copy_GBps"] == 5000.0 and r0["time_covered"] == 0.0

@@ -66,33 +66,59 @@ def test_gen_chunked_ranges_equal_full():
         assert np.array_equal(hh.cpu().numpy(), full_h[a:b].cpu().numpy())
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium"])
-def test_gen_screened_matches_oracle(name):
-    sci = require_gpu()
-    s = system(name)
-    h = ham(name)
-    dets = s.dets if name == "tiny" else s.dets[pick_sources(s.dets.shape[0], 16, 9)]
-    ok, oh, _ = oracle.gen_coupled(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
-    eps = float(np.quantile(np.abs(oh), 0.87))
-    say(f"gen screened {name}: eps={eps:.4e}")
+def _srckey(src, keys):
+    """(source, key words) rows as a structured int64 array: sorting it orders the rows
+    lexicographically, so two multisets compare equal exactly when their sorts do."""
+    m = np.ascontiguousarray(np.concatenate([np.asarray(src, dtype=np.int64)[:, None], keys.view(np.int64)], axis=1))
+    return m.view([(f"f{i}", np.int64) for i in range(m.shape[1])]).ravel()
+
+
+def _screened_check(sci, h, n_orb, na, nb, h1, eri, dets, quantile=0.87):
+    """Screened generation (|H| > eps kept, compacted in any order) against the oracle's
+    dense output filtered by the same rule, compared as (source, key) multisets with
+    the values matched entry by entry; entries within 1e-12 of eps are left out on
+    both sides (rounding may decide them either way).  Then the overflow case:
+    capacity below the kept count."""
+    ok, oh, _ = oracle.gen_coupled(n_orb, na, nb, h1, eri, dets)
+    eps = float(np.quantile(np.abs(oh), quantile))
     keys, hij, src, n_out, flags = _gen(sci, h, dets, eps=eps)
     assert sci.check_flags(flags, "gen") == 0
     n = int(n_out.item())
-    nc = h.n_coupled
-    osrc = np.repeat(np.arange(dets.shape[0]), nc)
-    keep = np.abs(oh) > eps
+    osrc = np.repeat(np.arange(dets.shape[0]), h.n_coupled)
     border = np.abs(np.abs(oh) - eps) < 1e-12
-    want = {(int(a), *map(int, k)) for a, k, kp, b in zip(osrc, ok, keep, border) if kp and not b}
-    gk = sci.keys_to_host(keys[:n])
-    got = {(int(a), *map(int, k)) for a, k in zip(src[:n].cpu().numpy(), gk)}
-    got_all = got
-    bset = {(int(a), *map(int, k)) for a, k, b in zip(osrc, ok, border) if b}
-    assert want == got_all - bset
-    assert n == len(got)
+    keep = (np.abs(oh) > eps) & ~border
+    g = _srckey(src[:n].cpu().numpy(), sci.keys_to_host(keys[:n]))
+    gh = hij[:n].cpu().numpy()
+    order = np.argsort(g, kind="stable")
+    g, gh = g[order], gh[order]
+    b = np.sort(_srckey(osrc[border], ok[border]))
+    if b.shape[0]:
+        i = np.minimum(np.searchsorted(b, g), b.shape[0] - 1)
+        g_keep = ~(b[i] == g)
+        g, gh = g[g_keep], gh[g_keep]
+    want = _srckey(osrc[keep], ok[keep])
+    worder = np.argsort(want, kind="stable")
+    want, want_h = want[worder], oh[keep][worder]
+    say(f"  eps={eps:.4e}: kept {n} of {ok.shape[0]} ({n / ok.shape[0]:.3f}), {b.shape[0]} borderline")
+    assert np.array_equal(g, want), "screened (source, key) multiset differs"
+    err = float(np.max(np.abs(gh - want_h), initial=0.0))
+    assert err <= H_TOL, f"kept values differ by {err:.3e}"
     # overflow: capacity below the kept count sets the flag and still reports the count
     keys2, _, _, n2, flags2 = _gen(sci, h, dets, eps=eps, capacity=max(1, n // 2))
     assert int(n2.item()) == n
     assert sci.check_flags(flags2, "gen", allow=sci.FLAG_OVERFLOW) & sci.FLAG_OVERFLOW
+    return n
+
+
+@pytest.mark.parametrize("name,n_src", [("tiny", None), ("medium", 16), ("large", 6)])
+def test_gen_screened_matches_oracle(name, n_src):
+    """Screened mode for one-word (tiny, medium) and two-word (large) keys."""
+    sci = require_gpu()
+    s = system(name)
+    h = ham(name)
+    dets = s.dets if n_src is None else s.dets[pick_sources(s.dets.shape[0], n_src, 9)]
+    say(f"gen screened {name} (W={h.W}): {dets.shape[0]} sources x {h.n_coupled}")
+    _screened_check(sci, h, s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, dets)
 
 
 def test_gen_bad_determinant_flag():
@@ -117,25 +143,44 @@ def test_gen_empty_range():
     assert int(n_out.item()) == 0 and keys.shape[0] == 0
 
 
-@pytest.mark.parametrize("n,na,nb", [(5, 1, 1), (6, 3, 0), (33, 2, 3), (40, 20, 19), (64, 3, 4)])
-def test_gen_edge_shapes(n, na, nb):
-    """Edge shapes: one electron per spin, an empty spin, W=2 boundary, half filling, n_orb=64."""
-    sci = require_gpu()
+def _edge_system(n, na, nb, n_dets=6):
     rng = np.random.Generator(np.random.PCG64(n + 100 * na + nb))
     h1 = si.make_h1(rng, n)
     eri = si.make_eri(rng, n, 6)
     W = si.n_words(n)
     picks = set()
-    while len(picks) < 6:
+    while len(picks) < n_dets:
         picks.add(si.pack_int(rng.choice(n, na, replace=False), rng.choice(n, nb, replace=False), n))
-    dets = si.sort_keys(si.ints_to_words(sorted(picks), W))
-    say(f"gen edge n={n} na={na} nb={nb}")
+    return h1, eri, si.sort_keys(si.ints_to_words(sorted(picks), W))
+
+
+# (50, 25, 25) and (64, 32, 32): n_alpha * v_alpha above 512, so the single excitations
+# are evaluated per lane instead of from the source's LDS table; (50, 10, 25) has only
+# the beta block above 512, which also sends both spins to the per-lane branch
+@pytest.mark.parametrize("n,na,nb", [(5, 1, 1), (6, 3, 0), (33, 2, 3), (40, 20, 19), (64, 3, 4),
+                                     (50, 25, 25), (50, 10, 25), (64, 32, 32)])
+def test_gen_edge_shapes(n, na, nb):
+    """Edge shapes: one electron per spin, an empty spin, W=2 boundary, half filling,
+    n_orb=64, and the per-lane single-excitation branch."""
+    sci = require_gpu()
+    h1, eri, dets = _edge_system(n, na, nb)
+    say(f"gen edge n={n} na={na} nb={nb}: {dets.shape[0]} sources x {sci.sci_n_coupled(n, na, nb)}")
     h = sci.Ham(n, na, nb, h1, eri)
     keys, hij, _, _, flags = _gen(sci, h, dets)
     assert sci.check_flags(flags, "gen") == 0
     ok, oh, _ = oracle.gen_coupled(n, na, nb, h1, eri, dets)
     assert np.array_equal(sci.keys_to_host(keys), ok)
     assert np.max(np.abs(hij.cpu().numpy() - oh), initial=0.0) <= H_TOL
+
+
+@pytest.mark.parametrize("n,na,nb", [(50, 25, 25), (64, 32, 32)])
+def test_gen_screened_per_lane_singles(n, na, nb):
+    """Screened mode (two-word keys) through the per-lane single-excitation branch."""
+    sci = require_gpu()
+    h1, eri, dets = _edge_system(n, na, nb, n_dets=3)
+    say(f"gen screened edge n={n} na={na} nb={nb}")
+    h = sci.Ham(n, na, nb, h1, eri)
+    _screened_check(sci, h, n, na, nb, h1, eri, dets)
 
 
 # ---------------------------------------------------------------------------
@@ -520,3 +565,51 @@ def test_gradient_dense_h_subset_large():
     say(f"  large subset: E gpu {e.item():.12f} dense {e_ref:.12f}")
     assert abs(e.item() - e_ref) <= E_TOL
     assert np.max(np.abs(g.cpu().numpy() - g_ref)) <= G_TOL
+
+
+def test_gradient_finite_differences_large():
+    """Central differences of the GPU energy over the whole large selected space (2e5
+    two-word determinants) along one seeded unit direction and 8 seeded coordinates,
+    h in {1e-4, 1e-5, 1e-6}, against the adjoint's g.v.  The difference quotient's
+    error is h^2/6 E''' (truncation) plus about 2 dE/(2h) (round-off of E): it must
+    shrink from h = 1e-4 to 1e-5 unless it is already at the round-off floor, and the
+    best step must reach 1e-7."""
+    sci = require_gpu()
+    s = system("large")
+    h = ham("large")
+    sel = sci.keys_to_device(s.dets)
+    psi = torch.from_numpy(s.psi).cuda()
+    e0, _, g, flags = sci.energy(h, sel, psi, want_hpsi=False)
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy") == 0
+    rng = np.random.Generator(np.random.PCG64(2604157684 + 7))
+    v = rng.standard_normal(s.psi.shape[0])
+    v /= np.linalg.norm(v)
+    coords = rng.choice(s.psi.shape[0], 8, replace=False)
+    dirs = [("unit", torch.from_numpy(v).cuda())]
+    for c in coords:
+        ec = torch.zeros_like(psi)
+        ec[int(c)] = 1.0
+        dirs.append((f"e_{int(c)}", ec))
+    steps = (1e-4, 1e-5, 1e-6)
+    # round-off of one energy evaluation, estimated from scale invariance E(c psi) = E(psi)
+    dE = max(abs(sci.energy(h, sel, c * psi, want_hpsi=False, want_grad=False)[0].item() - e0.item())
+             for c in (1.0 + 1e-3, 1.0 - 1e-3, 3.0))
+    floor = 4.0 * dE / steps[1]  # round-off part of the quotient's error at h = 1e-5, with margin
+    say(f"  energy round-off {dE:.2e} -> floor at h=1e-5: {floor:.2e}")
+    worst_best = 0.0
+    for name, d in dirs:
+        gv = float(torch.dot(g, d).item())
+        errs = []
+        for hstep in steps:
+            ep = sci.energy(h, sel, psi + hstep * d, want_hpsi=False, want_grad=False)[0].item()
+            em = sci.energy(h, sel, psi - hstep * d, want_hpsi=False, want_grad=False)[0].item()
+            errs.append(abs((ep - em) / (2 * hstep) - gv))
+        say(f"  {name}: g.v = {gv:+.6e}, |FD - g.v| at h = 1e-4, 1e-5, 1e-6: "
+            + ", ".join(f"{x:.2e}" for x in errs))
+        best = min(errs)
+        worst_best = max(worst_best, best)
+        assert best <= 1e-7, f"{name}: finite differences do not reach the adjoint gradient"
+        # O(h^2): a tenfold smaller step cuts the error unless round-off already dominates
+        assert errs[1] <= max(0.1 * errs[0], floor, 1e-12), f"{name}: error does not fall with h"
+    say(f"  worst best-step error {worst_best:.2e}, E = {e0.item():.12f}")

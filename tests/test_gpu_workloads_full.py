@@ -2,10 +2,12 @@
 
 Medium workload: the whole step's generation (2.51e9 candidates) and its dedup-merge
 into S.  Large workload: one 32,768-source mini-batch (1.18e10 candidates) streamed
-in pool chunks of 2^30 into S.  The oracle computes sampled sources one by one; the
-sets are checked exactly on whole key ranges against a library sort of every
-candidate that falls in the range (the candidates of the large mini-batch are
-regenerated chunk by chunk for that), and as sorted sets at full size.
+in pool chunks of 2^30 into S.  The oracle computes sampled sources one by one.
+Every key of each union is checked: the key space is cut into ranges at union keys,
+and in each range the union must equal a library sort + unique of every candidate
+(and selected key) that falls in it (the large mini-batch's candidates are
+regenerated chunk by chunk for that); the range counts must add up to the union's
+size, and the union is strictly ascending at full size.
 """
 import numpy as np
 import pytest
@@ -78,27 +80,37 @@ def test_medium_full_generation_and_dedup():
     # every selected determinant is in the union
     pos = torch.searchsorted(u, sel[:, 0])
     assert bool((pos < n).all()) and bool((u[pos.clamp(max=n - 1)] == sel[:, 0]).all())
-    # exact on whole ranges: the union's keys in [u[i], u[j]) are the sorted unique
-    # candidates and selected keys in that range
+    # every union key, checked exactly: the key space is cut into R ranges at union keys
+    # (the first range open below, the last open above), and the union's keys in each
+    # range are the sorted unique candidates and selected keys that fall in it
     R = 6
     cuts = [(r * n) // R for r in range(R + 1)]
+    bounds = [None] + [int(u[cuts[r]].item()) for r in range(1, R)] + [None]
     checked = 0
-    for r in (0, 2, R - 1):
-        i, j = cuts[r], cuts[r + 1]
-        lo = int(u[i].item())
-        hi = int(u[j].item()) if j < n else None
+    for r in range(R):
+        lo, hi = bounds[r], bounds[r + 1]
+
+        def inside(k):
+            m = torch.ones_like(k, dtype=torch.bool)
+            if lo is not None:
+                m &= k >= lo
+            if hi is not None:
+                m &= k < hi
+            return m
+
         parts = []
         for a in range(0, total, SLICE):
             k = keys[a:a + SLICE, 0]
-            m = k >= lo if hi is None else (k >= lo) & (k < hi)
-            parts.append(k[m])
+            parts.append(k[inside(k)])
         sk = sel[:, 0]
-        parts.append(sk[(sk >= lo) if hi is None else (sk >= lo) & (sk < hi)])
+        parts.append(sk[inside(sk)])
         expect = torch.unique(torch.cat(parts), sorted=True)
+        i, j = cuts[r], cuts[r + 1]
         assert torch.equal(expect, u[i:j]), f"union differs in range {r}"
-        checked += j - i
+        checked += expect.shape[0]
         del parts, expect
-    say(f"  {checked} union keys checked exactly in 3 of {R} ranges")
+    assert checked == n, f"ranges hold {checked} unique keys, the union {n}"
+    say(f"  all {n} union keys checked exactly in {R} ranges")
     del keys, union, u
     _free()
 
@@ -129,39 +141,55 @@ def test_large_streamed_minibatch_exact_ranges():
         up = (h1[1:] > h1[:-1]) | ((h1[1:] == h1[:-1]) & (l1[1:] > l1[:-1]))
         assert bool(up.all()), "union not strictly ascending"
         del h1, l1, up
-    # exact on three ranges of the union: regenerate every candidate of the mini-batch,
-    # chunk by chunk, and keep those inside [u[i], u[j])
-    ranges = []
-    for f in (0.2, 0.5, 0.8):
-        i = int(f * n)
-        j = min(i + 3_000_000, n)
-        lo = _rows_order(union[i, 1], union[i, 0])
-        hi = _rows_order(union[j, 1], union[j, 0]) if j < n else None
-        ranges.append((i, j, lo, hi))
-    parts = [[] for _ in ranges]
-
-    def take(k, out):
-        w1, w0 = _rows_order(k[:, 1], k[:, 0])
-        for (i, j, lo, hi), p in zip(ranges, out):
-            m = (w1 > lo[0]) | ((w1 == lo[0]) & (w0 >= lo[1]))
-            if hi is not None:
-                m &= (w1 < hi[0]) | ((w1 == hi[0]) & (w0 < hi[1]))
-            p.append(torch.stack([w1[m], w0[m]], dim=1))
-
-    for a in range(0, total, chunk):
-        b = min(a + chunk, total)
-        k, _, _, n_k, fl = sci.gen_coupled(h, dets, exc_begin=a, exc_end=b)
-        torch.cuda.synchronize()
-        assert sci.check_flags(fl, "gen") == 0 and int(n_k.item()) == b - a
-        for c in range(0, b - a, SLICE):
-            take(k[c:c + SLICE], parts)
-        del k
-    take(sel, parts)
-    for (i, j, _, _), p in zip(ranges, parts):
-        expect = _sort_unique_rows(torch.cat(p))
-        w1, w0 = _rows_order(union[i:j, 1], union[i:j, 0])
-        got = torch.stack([w1, w0], dim=1)
-        assert torch.equal(expect, got), f"union differs in range [{i}, {j})"
-        say(f"  range [{i}, {j}): {j - i} keys exact from {sum(x.shape[0] for x in p)} candidates")
-    del parts, union
+    # every union key, checked exactly.  The key space is cut into ranges at top-word
+    # values of union keys (the key order is the top word first), so a candidate's
+    # range follows from its top word alone; the union's keys of one range are a
+    # contiguous slice.  Per group of ranges, every candidate of the mini-batch is
+    # regenerated chunk by chunk and those of the group's ranges are kept; each range
+    # is then sorted and made unique by the library sort and compared with its slice.
+    hi = union[:n, 1].contiguous()
+    R = 16
+    hb = torch.unique(hi[torch.tensor([(r * n) // R for r in range(1, R)], device="cuda")], sorted=True)
+    n_ranges = hb.shape[0] + 1
+    starts = torch.searchsorted(hi, hb).tolist()
+    slices = list(zip([0] + starts, starts + [n]))
+    del hi
+    _free()
+    sel_ids = torch.searchsorted(hb, sel[:, 1].contiguous(), right=True)
+    G = 4
+    checked = 0
+    for g0 in range(0, n_ranges, G):
+        group = list(range(g0, min(g0 + G, n_ranges)))
+        parts = {r: [] for r in group}
+        for a in range(0, total, chunk):
+            b = min(a + chunk, total)
+            k, _, _, n_k, fl = sci.gen_coupled(h, dets, exc_begin=a, exc_end=b)
+            torch.cuda.synchronize()
+            assert sci.check_flags(fl, "gen") == 0 and int(n_k.item()) == b - a
+            for c in range(0, b - a, SLICE):
+                kc = k[c:c + SLICE]
+                ids = torch.searchsorted(hb, kc[:, 1].contiguous(), right=True)
+                for r in group:
+                    parts[r].append(kc[ids == r])
+                del ids
+            del k
+            _free()
+        for r in group:
+            parts[r].append(sel[sel_ids == r])
+            cand = torch.cat(parts.pop(r))
+            got_n = cand.shape[0]
+            w1, w0 = _rows_order(cand[:, 1], cand[:, 0])
+            del cand
+            expect = _sort_unique_rows(torch.stack([w1, w0], dim=1))
+            del w1, w0
+            i, j = slices[r]
+            u1, u0 = _rows_order(union[i:j, 1], union[i:j, 0])
+            assert torch.equal(expect, torch.stack([u1, u0], dim=1)), f"union differs in range {r} [{i}, {j})"
+            checked += expect.shape[0]
+            say(f"  range {r} [{i}, {j}): {j - i} keys exact from {got_n} candidates")
+            del expect, u1, u0
+            _free()
+    assert checked == n, f"ranges hold {checked} unique keys, the union {n}"
+    say(f"  all {n} union keys checked exactly in {n_ranges} ranges")
+    del union
     _free()

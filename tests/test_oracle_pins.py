@@ -38,6 +38,31 @@ def _closed_form_count(n, na, nb):
             + math.comb(nb, 2) * math.comb(vb, 2) + na * va * nb * vb)
 
 
+def test_tiny_regression_fixture():
+    """The stored tiny-workload results (written once by tests/golden/make_golden.py
+    from the oracle) still come out of the oracle: a regression pin of the oracle and
+    of the seeded input generator together.  Counts that the mathematics fixes are
+    checked against the closed form besides: 200 sources x 140 coupled candidates,
+    and the union with S is the whole 441-determinant space (C(7,5)^2)."""
+    import hashlib
+    with open(os.path.join(GOLDEN, "tiny_oracle.json")) as f:
+        ref = json.load(f)
+    wl = si.WORKLOADS["tiny"]
+    s = si.make_system(wl)
+    keys, hij, _ = oracle.gen_coupled(wl.n_orb, wl.n_alpha, wl.n_beta, s.h1, s.eri, s.dets)
+    assert keys.shape[0] == ref["n_candidates"] == 200 * _closed_form_count(7, 5, 5)
+    assert hashlib.sha256(np.ascontiguousarray(keys).tobytes()).hexdigest() == ref["keys_sha256"]
+    assert np.allclose(hij[:8], ref["hij_first"], rtol=0, atol=1e-13)
+    assert abs(float(np.abs(hij).sum()) - ref["hij_abs_sum"]) <= 1e-9
+    u, nov = oracle.dedup_merge(wl.W, keys, s.dets)
+    assert u.shape[0] == ref["n_unique_with_sel"] == math.comb(7, 5) ** 2
+    assert nov.shape[0] == ref["n_novel"] == 441 - s.dets.shape[0]
+    e, hp, g = oracle.energy(wl.n_orb, wl.n_alpha, wl.n_beta, s.h1, s.eri, s.dets, s.psi)
+    assert abs(e - ref["energy"]) <= 1e-12
+    assert np.allclose(hp[:4], ref["hpsi_first"], rtol=0, atol=1e-12)
+    assert np.allclose(g[:4], ref["grad_first"], rtol=0, atol=1e-12)
+
+
 def test_golden_counts_fixture():
     with open(os.path.join(GOLDEN, "coupled_counts.json")) as f:
         data = json.load(f)
