@@ -292,27 +292,41 @@ int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t n_dets,
 /*
  * Reverse index (paper section 2.2: every coupled configuration mapped to its
  * entry in the unique set; section 4.3 stage 3: each original configuration
- * searched in the unique set).
+ * searched in the unique set).  Two kinds of index return the same answer:
  *
- * sci_index_bytes: size of an index over at most set_bound keys (a header and
- * an open-addressing table of 2^ceil(log2(2*set_bound)) slots of 16 bytes for
- * W=1, 32 bytes for W=2; at least 64 slots).
+ *   hash    an open-addressing table of 2^ceil(log2(2*set_bound)) slots of 16
+ *           bytes (W=1) or 32 bytes (W=2), at least 64 slots, after a 256-byte
+ *           header: sci_index_bytes(n_words, set_bound) bytes.  One lookup reads
+ *           about one slot.  Independent of the set once built.
+ *   sorted  the paper's search of the sorted set: a 256-byte header and every
+ *           256th set key (1/256 of the set's bytes):
+ *           sci_index_bytes_sorted(n_words, set_bound) bytes.  A lookup searches
+ *           a top level of those samples in LDS, then the samples, then one
+ *           256-key block of the set itself, so the set must stay in place and
+ *           unchanged while the index is used.  For sets whose table would not
+ *           fit beside them (3.06e9 two-word keys: a 275 GB table, a 191 MB
+ *           sorted index).
  *
- * sci_index_build: load the strictly ascending set (device [*n_set][W], count
- * on the device) into `index` (device, caller-owned, at least
- * sci_index_bytes(n_words, set_bound) bytes).  If *n_set > set_bound,
- * SCI_FLAG_OVERFLOW is set and only the first set_bound keys are indexed.
- * The set must stay unchanged while the index is used.
+ * sci_index_build: index the strictly ascending set (device [*n_set][W], count
+ * on the device) into `index` (device, caller-owned).  The kind follows from the
+ * buffer: index_bytes >= sci_index_bytes(n_words, set_bound) builds the hash
+ * kind, else index_bytes >= sci_index_bytes_sorted(...) the sorted kind, else
+ * SCI_ECAPACITY.  If *n_set > set_bound, SCI_FLAG_OVERFLOW is set and only the
+ * first set_bound keys are indexed.  The set must stay unchanged while the index
+ * is used.
  *
  * sci_index_lookup: idx[i] (device int64) = position of cand[i] in the set,
  * or -1 when the key is not in it, for i < n_cand; cand is device
- * [n_cand][W], any order.  Deterministic (positions, not probe order).  An
- * index buffer that sci_index_build did not fill for this n_words gives -1
- * for every candidate (the kernel checks the header against index_bytes).
+ * [n_cand][W], any order.  Deterministic (positions, not probe order).  The
+ * kind is read from the index's device header (the kernels of both kinds are
+ * enqueued; the one that does not match returns at once).  An index buffer that
+ * sci_index_build did not fill for this n_words and a size that fits in
+ * index_bytes gives -1 for every candidate.
  * Errors: SCI_EINVAL, SCI_EUNSUPPORTED (n_words), SCI_ECAPACITY (index too
  * small), SCI_EHIP.
  */
 size_t sci_index_bytes(int32_t n_words, int64_t set_bound);
+size_t sci_index_bytes_sorted(int32_t n_words, int64_t set_bound);
 int32_t sci_index_build(int32_t n_words, const uint64_t *set, const int64_t *n_set, int64_t set_bound,
                         void *index, size_t index_bytes, uint32_t *dev_flags, sci_stream_t stream);
 int32_t sci_index_lookup(int32_t n_words, const void *index, size_t index_bytes,

@@ -65,6 +65,8 @@ _lib.sci_stream_dedup.argtypes = [_P, _P, _i64, _i64, _i64, _i64, _P, _P, _P, _P
 _lib.sci_stream_dedup.restype = _i32
 _lib.sci_index_bytes.argtypes = [_i32, _i64]
 _lib.sci_index_bytes.restype = _sz
+_lib.sci_index_bytes_sorted.argtypes = [_i32, _i64]
+_lib.sci_index_bytes_sorted.restype = _sz
 _lib.sci_index_build.argtypes = [_i32, _P, _P, _i64, _P, _sz, _P, _P]
 _lib.sci_index_build.restype = _i32
 _lib.sci_index_lookup.argtypes = [_i32, _P, _sz, _P, _i64, _P, _P]
@@ -466,15 +468,39 @@ def sci_topk(n_words, keys, psi, n, k, out_keys, out_psi, n_out, capacity, works
                          _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_topk")
 
 
-def build_index(set_keys: torch.Tensor, n_set: torch.Tensor, set_bound: int, W: int, flags=None):
-    """Reverse-index table over the strictly ascending set (count n_set on the device)."""
+def sci_index_bytes_sorted(n_words: int, set_bound: int) -> int:
+    return int(_lib.sci_index_bytes_sorted(n_words, set_bound))
+
+
+def build_index(set_keys: torch.Tensor, n_set: torch.Tensor, set_bound: int, W: int, flags=None, kind="auto",
+                reserve_bytes=8 << 30):
+    """Reverse index over the strictly ascending set (count n_set on the device).
+
+    kind "hash": an open-addressing table (32-64 bytes per key); "sorted": samples of
+    the sorted set (1/256 of its bytes) searched together with the set itself, which
+    must then stay unchanged while the index is used; "auto": the table when it fits in
+    free device memory with `reserve_bytes` to spare, else the sorted kind."""
     dev = set_keys.device
-    nbytes = sci_index_bytes(W, set_bound)
+    if kind == "auto":
+        free_bytes = torch.cuda.mem_get_info(dev)[0]
+        kind = "hash" if sci_index_bytes(W, set_bound) + reserve_bytes <= free_bytes else "sorted"
+    if kind not in ("hash", "sorted"):
+        raise ValueError(f"unknown index kind {kind!r}")
+    nbytes = sci_index_bytes(W, set_bound) if kind == "hash" else sci_index_bytes_sorted(W, set_bound)
+    if kind == "sorted":
+        # the library picks the kind from the buffer size: stay below a table's size
+        nbytes = min(nbytes, sci_index_bytes(W, set_bound) - 1)
     index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     if flags is None:
         flags = new_flags(dev)
     sci_index_build(W, set_keys, n_set, set_bound, index, nbytes, flags)
     return index, flags
+
+
+def index_kind(index: torch.Tensor) -> str:
+    """"hash" or "sorted": the kind of a built index (reads its device header)."""
+    tag = int(index[16:24].view(torch.int64).item())
+    return "sorted" if tag == 0x534F525445444958 else "hash"
 
 
 def inverse_map(index: torch.Tensor, cand: torch.Tensor, W: int):

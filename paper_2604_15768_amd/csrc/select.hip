@@ -3,11 +3,17 @@
 // candidates with the largest inferred amplitudes; section 4.3, stages 2-3).
 //
 // Reverse index.  The paper builds it by searching each original
-// configuration in the unique set.  Here the unique set is first loaded into
-// an open-addressing table in HBM (key -> position in the sorted set, linear
-// probing, load factor <= 1/2); a lookup then costs about one random sector
-// read instead of ~log2|U| dependent reads of a binary search.  The answer is
-// the same: the position of the key in the sorted set, or -1.
+// configuration in the unique set.  Two kinds of index give that answer (the
+// position of the key in the sorted set, or -1):
+//   hash   the unique set loaded into an open-addressing table in HBM (key ->
+//          position, linear probing, load factor <= 1/2): a lookup costs about
+//          one random sector read instead of ~log2|U| dependent reads; the table
+//          takes 32-64 bytes per set key.
+//   sorted the paper's search of the sorted set itself, for sets whose table
+//          would not fit next to them: the index holds every 256th set key (1/256
+//          of the set's bytes, small enough to stay in the last-level cache); a
+//          lookup finds its 256-key block by searching a top level of those
+//          samples held in LDS and then the samples, and searches the block.
 //
 // Top-K.  Entries are ranked by |psi| descending, equal magnitudes by key
 // ascending.  Each entry's rank value is a composite of (64 + 64W) bits: the
@@ -36,7 +42,13 @@ struct SlotCfg {
     static constexpr int IDX = W;  // word holding position + 1
 };
 
-constexpr size_t kIndexHeader = 256;  // int64 slot count (power of two), int32 W
+// header (int64 words): [0] hash slot count (power of two; 0 for the sorted kind),
+// [1] W, [2] kind tag (kSortedTag for the sorted kind), sorted kind only: [3] set
+// size, [4] set address, [5] sample stride, [6] sample count
+constexpr size_t kIndexHeader = 256;
+constexpr int64_t kSortedTag = 0x534F525445444958ll;  // "SORTEDIX"
+constexpr int64_t kSortedStride = 256;                 // every 256th set key is a sample
+constexpr int kTopLevel = 2048;                        // samples' top level held in LDS
 
 // SplitMix64 output mixer (Steele, Lea, Flood, "Fast splittable pseudorandom
 // number generators", 2014), applied to the folded key words.
@@ -64,6 +76,7 @@ __global__ void index_clear_kernel(uint64_t *tab, int64_t words, int64_t *hdr, i
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr[0] = T;
         hdr[1] = W;
+        hdr[2] = 0;
     }
 }
 
@@ -114,6 +127,7 @@ template <int W>
 __global__ void index_lookup_kernel(const uint64_t *tab, const int64_t *hdr, int64_t tmax, const uint64_t *cand,
                                     int64_t n, int64_t *idx) {
     using S = SlotCfg<W>;
+    if (hdr[2] == kSortedTag) return;  // a sorted index: index_lookup_sorted_kernel answers
     int64_t T = hdr[0];
     if (T < 64 || (T & (T - 1)) != 0 || T > tmax || hdr[1] != W) T = 0;
     const uint64_t mask = (uint64_t)T - 1;
@@ -134,6 +148,92 @@ __global__ void index_lookup_kernel(const uint64_t *tab, const int64_t *hdr, int
                 break;
             }
             h = (h + 1) & mask;
+        }
+        idx[i] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse index: search of the sorted set (samples of every kSortedStride-th key)
+// ---------------------------------------------------------------------------
+
+static int64_t sorted_samples(int64_t set_bound) { return ceil_div(std::max<int64_t>(set_bound, 0), kSortedStride); }
+
+template <int W>
+__global__ void index_sample_kernel(const uint64_t *set, const int64_t *n_set, int64_t bound, uint64_t *samples,
+                                    int64_t *hdr, uint32_t *flags) {
+    const int64_t n_all = *n_set;
+    const int64_t n = n_all < bound ? n_all : bound;
+    const int64_t m = ceil_div_dev(n, kSortedStride);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride)
+        store_key<W>(samples, t, load_key<W>(set, t * kSortedStride));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (n_all > bound) atomicOr(flags, SCI_FLAG_OVERFLOW);
+        hdr[0] = 0;
+        hdr[1] = W;
+        hdr[2] = kSortedTag;
+        hdr[3] = n;
+        hdr[4] = (int64_t)(uintptr_t)set;
+        hdr[5] = kSortedStride;
+        hdr[6] = m;
+    }
+}
+
+// number of keys in a[lo, hi) that are <= k (a ascending), by binary search
+template <int W>
+__device__ __forceinline__ int64_t count_le(const uint64_t *a, int64_t lo, int64_t hi, const Key<W> &k) {
+    const int64_t base = lo;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (key_less<W>(k, load_key<W>(a, mid))) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo - base;
+}
+
+// max_samples: the most samples the caller's buffer can hold.  A header that is not a
+// sorted index for this W and buffer size gives -1 everywhere.
+template <int W>
+__global__ __launch_bounds__(256) void index_lookup_sorted_kernel(const int64_t *hdr, int64_t max_samples,
+                                                                  const uint64_t *samples, const uint64_t *cand,
+                                                                  int64_t n, int64_t *idx) {
+    __shared__ Key<W> top[kTopLevel];
+    if (hdr[2] != kSortedTag) return;  // a hash index: index_lookup_kernel answers
+    const int64_t n_set = hdr[3], m = hdr[6];
+    const uint64_t *set = (const uint64_t *)(uintptr_t)hdr[4];
+    const bool valid = hdr[1] == W && hdr[5] == kSortedStride && m >= 0 && m <= max_samples && n_set >= 0 &&
+                       m == ceil_div_dev(n_set, kSortedStride) && (n_set == 0 || set != nullptr);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (!valid || m == 0) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) idx[i] = -1;
+        return;
+    }
+    // top level: every R-th sample, at most kTopLevel of them
+    const int64_t R = ceil_div_dev(m, kTopLevel);
+    const int nt = (int)ceil_div_dev(m, R);
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) top[t] = load_key<W>(samples, (int64_t)t * R);
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const Key<W> k = load_key<W>(cand, i);
+        // top entries <= k
+        int lo = 0, hi = nt;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key_less<W>(k, top[mid])) hi = mid;
+            else lo = mid + 1;
+        }
+        int64_t r = -1;
+        if (lo > 0) {  // else k is below the first set key
+            // the last sample <= k lies in the top entry's block of R samples
+            const int64_t s0 = (int64_t)(lo - 1) * R;
+            const int64_t s1 = s0 + R < m ? s0 + R : m;
+            const int64_t t = s0 + count_le<W>(samples, s0, s1, k) - 1;  // >= s0: samples[s0] <= k
+            // and the key, if present, in that sample's block of set keys
+            const int64_t b0 = t * kSortedStride;
+            const int64_t b1 = b0 + kSortedStride < n_set ? b0 + kSortedStride : n_set;
+            const int64_t c = count_le<W>(set, b0, b1, k);  // >= 1: set[b0] = samples[t] <= k
+            if (key_eq<W>(load_key<W>(set, b0 + c - 1), k)) r = b0 + c - 1;
         }
         idx[i] = r;
     }
@@ -409,6 +509,11 @@ extern "C" size_t sci_index_bytes(int32_t n_words, int64_t set_bound) {
     return kIndexHeader + (size_t)index_slots(set_bound) * words * 8;
 }
 
+extern "C" size_t sci_index_bytes_sorted(int32_t n_words, int64_t set_bound) {
+    if (n_words < 1 || n_words > SCI_MAX_WORDS || set_bound < 0) return 0;
+    return kIndexHeader + (size_t)std::max<int64_t>(sorted_samples(set_bound), 1) * n_words * 8;
+}
+
 extern "C" int32_t sci_index_build(int32_t n_words, const uint64_t *set, const int64_t *n_set, int64_t set_bound,
                                    void *index, size_t index_bytes, uint32_t *dev_flags, sci_stream_t stream) {
     set_error("");
@@ -418,8 +523,23 @@ extern "C" int32_t sci_index_build(int32_t n_words, const uint64_t *set, const i
     if (!n_set || !index || !dev_flags || (set_bound > 0 && !set))
         return fail(SCI_EINVAL, "sci_index_build: NULL pointer argument");
     const size_t need = sci_index_bytes(n_words, set_bound);
-    if (index_bytes < need) return fail(SCI_ECAPACITY, "sci_index_build: index %zu < %zu bytes", index_bytes, need);
+    const size_t need_sorted = sci_index_bytes_sorted(n_words, set_bound);
+    if (index_bytes < need_sorted)
+        return fail(SCI_ECAPACITY, "sci_index_build: index %zu < %zu bytes (sorted kind; %zu for a hash table)",
+                    index_bytes, need_sorted, need);
     hipStream_t st = (hipStream_t)stream;
+    if (index_bytes < need) {
+        // room for the samples but not for a table: the sorted kind
+        int64_t *hdr = (int64_t *)index;
+        uint64_t *samples = (uint64_t *)((char *)index + kIndexHeader);
+        const unsigned g = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, ceil_div(sorted_samples(set_bound), 256)));
+        if (n_words == 1)
+            SCI_LAUNCH(index_sample_kernel<1>, dim3(g), dim3(256), 0, st, set, n_set, set_bound, samples, hdr, dev_flags);
+        else
+            SCI_LAUNCH(index_sample_kernel<2>, dim3(g), dim3(256), 0, st, set, n_set, set_bound, samples, hdr, dev_flags);
+        SCI_HIP_TRY(hipGetLastError());
+        return SCI_OK;
+    }
     const int64_t T = index_slots(set_bound);
     const int words = n_words == 1 ? SlotCfg<1>::WORDS : SlotCfg<2>::WORDS;
     int64_t *hdr = (int64_t *)index;
@@ -440,20 +560,34 @@ extern "C" int32_t sci_index_lookup(int32_t n_words, const void *index, size_t i
         return fail(n_words < 1 ? SCI_EINVAL : SCI_EUNSUPPORTED, "sci_index_lookup: n_words=%d", n_words);
     if (n_cand < 0) return fail(SCI_EINVAL, "sci_index_lookup: negative n_cand");
     if (!index || (n_cand > 0 && (!cand || !idx))) return fail(SCI_EINVAL, "sci_index_lookup: NULL pointer argument");
-    if (index_bytes < sci_index_bytes(n_words, 0))
-        return fail(SCI_ECAPACITY, "sci_index_lookup: index buffer of %zu bytes holds no table", index_bytes);
+    if (index_bytes < sci_index_bytes_sorted(n_words, 0))
+        return fail(SCI_ECAPACITY, "sci_index_lookup: index buffer of %zu bytes holds no index", index_bytes);
     if (n_cand == 0) return SCI_OK;
     hipStream_t st = (hipStream_t)stream;
     const int64_t *hdr = (const int64_t *)index;
     const uint64_t *tab = (const uint64_t *)((const char *)index + kIndexHeader);
     const int words = n_words == 1 ? SlotCfg<1>::WORDS : SlotCfg<2>::WORDS;
-    int64_t tmax = 64;
-    while (kIndexHeader + (size_t)(2 * tmax) * words * 8 <= index_bytes) tmax <<= 1;
+    // the most hash slots / samples the buffer holds (what a valid header can claim)
+    int64_t tmax = 0;
+    if (index_bytes >= sci_index_bytes(n_words, 0)) {
+        tmax = 64;
+        while (kIndexHeader + (size_t)(2 * tmax) * words * 8 <= index_bytes) tmax <<= 1;
+    }
+    const int64_t smax = (int64_t)((index_bytes - kIndexHeader) / ((size_t)n_words * 8));
+    // the index kind is in the device header: both kernels are enqueued and the one that
+    // does not match it returns at once
     const unsigned g = (unsigned)std::min<int64_t>(1 << 16, ceil_div(n_cand, 256));
-    if (n_words == 1)
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    // the sorted kernel loads its top level once per workgroup: a small persistent grid
+    const unsigned gs = (unsigned)std::min<int64_t>((int64_t)std::max(n_cu, 1) * 8, ceil_div(n_cand, 256));
+    if (n_words == 1) {
         SCI_LAUNCH(index_lookup_kernel<1>, dim3(g), dim3(256), 0, st, tab, hdr, tmax, cand, n_cand, idx);
-    else
+        SCI_LAUNCH(index_lookup_sorted_kernel<1>, dim3(gs), dim3(256), 0, st, hdr, smax, tab, cand, n_cand, idx);
+    } else {
         SCI_LAUNCH(index_lookup_kernel<2>, dim3(g), dim3(256), 0, st, tab, hdr, tmax, cand, n_cand, idx);
+        SCI_LAUNCH(index_lookup_sorted_kernel<2>, dim3(gs), dim3(256), 0, st, hdr, smax, tab, cand, n_cand, idx);
+    }
     SCI_HIP_TRY(hipGetLastError());
     return SCI_OK;
 }

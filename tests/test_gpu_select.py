@@ -16,9 +16,14 @@ def _sorted_unique(rng, n, W, hi):
     return k[order]
 
 
+# the sorted kind (the paper's search of the sorted set) on sets below one sample block,
+# not a multiple of the 256-key block, and above 2048 x 256 keys (a top level of every
+# R-th sample, R > 1)
+@pytest.mark.parametrize("kind", ["hash", "sorted"])
 @pytest.mark.parametrize("W,n_set,n_cand", [(1, 0, 10), (1, 1, 1000), (1, 5000, 100_000), (2, 3000, 50_000),
-                                            (1, 200_000, 1_000_000)])
-def test_inverse_map_matches_oracle(W, n_set, n_cand):
+                                            (1, 200_000, 1_000_000), (1, 3_000_001, 2_000_000),
+                                            (2, 700_000, 500_000)])
+def test_inverse_map_matches_oracle(W, n_set, n_cand, kind):
     sci = require_gpu()
     rng = np.random.Generator(np.random.PCG64(100 + n_set))
     hi = max(4 * n_set, 8)
@@ -27,10 +32,14 @@ def test_inverse_map_matches_oracle(W, n_set, n_cand):
     if n_set:  # half the candidates are members of the set, in random order and repeated
         cand[: n_cand // 2] = u[rng.integers(0, u.shape[0], size=n_cand // 2)]
         rng.shuffle(cand)
-    say(f"inverse map W={W} |U|={u.shape[0]} n={n_cand}")
+    if n_set > 1:  # keys below the first and above the last set key
+        cand[0] = np.zeros(W, dtype=np.uint64)
+        cand[1] = np.full(W, np.iinfo(np.uint64).max, dtype=np.uint64)
+    say(f"inverse map ({kind}) W={W} |U|={u.shape[0]} n={n_cand}")
     ud = sci.keys_to_device(u) if u.shape[0] else torch.zeros((1, W), dtype=torch.int64, device="cuda")
     nd = torch.tensor([u.shape[0]], dtype=torch.int64, device="cuda")
-    index, flags = sci.build_index(ud, nd, u.shape[0], W)
+    index, flags = sci.build_index(ud, nd, u.shape[0], W, kind=kind)
+    assert sci.index_kind(index) == kind
     idx = sci.inverse_map(index, sci.keys_to_device(cand), W)
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "index") == 0
@@ -63,11 +72,12 @@ def test_inverse_map_of_generated_candidates():
     assert np.array_equal(got, oracle.inverse_map(s.W, u, k))
 
 
-def test_index_overflow_flag():
+@pytest.mark.parametrize("kind", ["hash", "sorted"])
+def test_index_overflow_flag(kind):
     sci = require_gpu()
     u = np.arange(1, 101, dtype=np.uint64).reshape(-1, 1)
     nd = torch.tensor([100], dtype=torch.int64, device="cuda")
-    index, flags = sci.build_index(sci.keys_to_device(u), nd, 50, 1)
+    index, flags = sci.build_index(sci.keys_to_device(u), nd, 50, 1, kind=kind)
     idx = sci.inverse_map(index, sci.keys_to_device(u), 1)
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "index", allow=sci.FLAG_OVERFLOW) & sci.FLAG_OVERFLOW

@@ -193,3 +193,83 @@ def test_large_streamed_minibatch_exact_ranges():
     say(f"  all {n} union keys checked exactly in {n_ranges} ranges")
     del union
     _free()
+
+
+def _strictly_ascending_rows(union, n):
+    for a in range(0, n - 1, SLICE):
+        b = min(a + SLICE + 1, n)
+        h1, l1 = _rows_order(union[a:b, 1], union[a:b, 0])
+        up = (h1[1:] > h1[:-1]) | ((h1[1:] == h1[:-1]) & (l1[1:] > l1[:-1]))
+        if not bool(up.all()):
+            return False
+        del h1, l1, up
+    return True
+
+
+def test_large_whole_selected_space_streamed():
+    """All 200,000 sources of the large workload (7.2e10 candidates) streamed in pool
+    chunks of 2^29 into one set on one GPU.  Checked at full size: no overflow, strictly
+    ascending, S contained; and exactly on two sampled key ranges (cut at top-word
+    values of union keys) against a library sort + unique of every candidate of the
+    whole stream that falls in them, regenerated chunk by chunk."""
+    sci = require_gpu()
+    s = system("large")
+    h = ham("large")
+    _free()
+    sel = sci.keys_to_device(s.dets)
+    n_src, chunk = sel.shape[0], 1 << 29
+    total = n_src * h.n_coupled
+    cap = 5_600_000_000
+    say(f"large, whole S: {total} candidates, chunks of {chunk}, set capacity {cap}")
+    union, n_union, flags = sci.stream_dedup(h, sel, chunk, sel, cap, dedup_stream=torch.cuda.Stream())
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "stream") == 0
+    n = int(n_union.item())
+    say(f"  union of {n} keys")
+    assert s.dets.shape[0] <= n <= cap
+    _free()
+    assert _strictly_ascending_rows(union, n), "union not strictly ascending"
+    # S is contained: each selected key sits at its searchsorted position
+    hi = union[:n, 1].contiguous()
+    # two sampled ranges of about 4e7 union keys, cut at top-word values
+    ranges = []
+    for f in (0.3, 0.7):
+        i0 = int(f * n)
+        lo_v = hi[i0]
+        hi_v = hi[min(i0 + 40_000_000, n - 1)]
+        if int(hi_v.item()) == int(lo_v.item()):
+            hi_v = lo_v + 1
+        i = int(torch.searchsorted(hi, lo_v.reshape(1)).item())
+        j = int(torch.searchsorted(hi, hi_v.reshape(1)).item())
+        ranges.append((int(lo_v.item()), int(hi_v.item()), i, j))
+    del hi
+    _free()
+    parts = [[] for _ in ranges]
+
+    def take(k):
+        w1 = k[:, 1]
+        for (lo, hi_, _, _), p in zip(ranges, parts):
+            m = (w1 >= lo) & (w1 < hi_)
+            p.append(k[m])
+
+    for a in range(0, total, chunk):
+        b = min(a + chunk, total)
+        k, _, _, n_k, fl = sci.gen_coupled(h, sel, exc_begin=a, exc_end=b)
+        assert int(n_k.item()) == b - a
+        take(k)
+        del k
+    torch.cuda.synchronize()
+    assert sci.check_flags(fl, "gen") == 0
+    take(sel)
+    for (lo, hi_, i, j), p in zip(ranges, parts):
+        cand = torch.cat(p)
+        w1, w0 = _rows_order(cand[:, 1], cand[:, 0])
+        expect = _sort_unique_rows(torch.stack([w1, w0], dim=1))
+        del cand, w1, w0
+        u1, u0 = _rows_order(union[i:j, 1], union[i:j, 0])
+        assert torch.equal(expect, torch.stack([u1, u0], dim=1)), f"union differs in [{i}, {j})"
+        say(f"  range [{i}, {j}): {j - i} keys exact from {sum(x.shape[0] for x in p)} candidates")
+        del expect, u1, u0
+        _free()
+    del parts, union
+    _free()
