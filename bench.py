@@ -645,12 +645,34 @@ def select_extras(torch, sci, keys, n_cand, union, n_union_dev, n_union, sel, n_
     return out
 
 
-def energy_extras(torch, sci, ham, sel, psi):
+def energy_methods(torch, sci, ham, sel, psi, reps):
+    """E + dE/dpsi with each membership method (pair screening, enumeration + search of
+    S) and the method the cost model picks for this shape."""
+    n_sel = sel.shape[0]
+    out = {"n_sel": n_sel, "n_coupled": ham.n_coupled,
+           "auto": {sci.ENERGY_PAIRS: "pairs", sci.ENERGY_ENUM: "enum"}[sci.sci_energy_method(ham, n_sel)]}
+    for name, m in (("pairs", sci.ENERGY_PAIRS), ("enum", sci.ENERGY_ENUM)):
+        fn = lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=True, method=m)
+        fn()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = _median_ms(fn, reps, torch)
+    out["faster"] = "pairs" if out["pairs_ms"] <= out["enum_ms"] else "enum"
+    return out
+
+
+def energy_extras(torch, sci, si, ham, sel, psi):
     """E and E + dE/dpsi over all of the large S: the plain entry point and the autograd path
-    (forward + backward, which recomputes H psi)."""
+    (forward + backward, which recomputes H psi); both membership methods on the large S
+    and on a small-orbital system (n_orb=10, 4a+4b, 17,000 determinants)."""
     n_sel = sel.shape[0]
     e_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=False), 5, torch)
     eg_ms = _median_ms(lambda: sci.energy(ham, sel, psi, want_hpsi=False, want_grad=True), 5, torch)
+    methods = {"large": energy_methods(torch, sci, ham, sel, psi, 1)}
+    wl = si.small_workload(10, 4, 4, n_sel=17_000, selection="levels")
+    sm = si.make_system(wl)
+    hs = sci.Ham(sm.n_orb, sm.n_alpha, sm.n_beta, sm.h1, sm.eri)
+    methods["small_10_4_4"] = energy_methods(torch, sci, hs, sci.keys_to_device(sm.dets),
+                                             torch.from_numpy(sm.psi).to(sel.device), 5)
 
     def auto():
         p = psi.clone().requires_grad_(True)
@@ -659,7 +681,7 @@ def energy_extras(torch, sci, ham, sel, psi):
 
     ag_ms = _median_ms(auto, 5, torch)
     return {"workload": f"large: E over all {n_sel} selected determinants", "n_sel": n_sel,
-            "energy_ms": e_ms, "energy_grad_ms": eg_ms, "autograd_fwd_bwd_ms": ag_ms}
+            "energy_ms": e_ms, "energy_grad_ms": eg_ms, "autograd_fwd_bwd_ms": ag_ms, "methods": methods}
 
 
 def batch_extras(args, torch, sci, si):
@@ -853,7 +875,7 @@ def main():
     result["extras"] = {}
     if "energy" in extras and ctx_large is not None:
         ham, sel, psi, _ = ctx_large
-        result["extras"]["energy_grad_large"] = energy_extras(torch, sci, ham, sel, psi)
+        result["extras"]["energy_grad_large"] = energy_extras(torch, sci, si, ham, sel, psi)
     ctx_large = None
     torch.cuda.empty_cache()
     if extras & {"medium", "select", "screened"}:

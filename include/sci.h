@@ -229,6 +229,32 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
                    uint32_t *dev_flags, sci_stream_t stream);
 
 /*
+ * How membership j in C_i is decided (both give H psi within rounding; each
+ * method's results repeat bit for bit):
+ *   SCI_ENERGY_PAIRS  pair screening: every (i, j) of S x S tested by one XOR +
+ *                     popcount (D_i and D_j differ in at most two electrons).
+ *   SCI_ENERGY_ENUM   enumeration + search (paper section 4.3: configurations
+ *                     searched in a sorted set): C_i generated for every i (the
+ *                     excitation order of sci_gen_coupled), each determinant
+ *                     searched in the sorted S.  |S| N_c searches against |S|^2
+ *                     tests: the faster one when N_c is small against |S|.
+ *   SCI_ENERGY_AUTO   the method a cost model picks for this shape:
+ *                     enumeration when N_c * 64 < n_sel, else pair screening
+ *                     (sci_energy always uses it; sci_energy_method reports it).
+ * sci_energy_ex is sci_energy with the method given; sci_energy_method returns
+ * the method SCI_ENERGY_AUTO picks for n_sel determinants of this handle (-1 for
+ * invalid arguments).
+ */
+#define SCI_ENERGY_AUTO 0
+#define SCI_ENERGY_PAIRS 1
+#define SCI_ENERGY_ENUM 2
+int32_t sci_energy_ex(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                      double *energy, double *h_psi, double *grad, int32_t method,
+                      void *workspace, size_t workspace_bytes,
+                      uint32_t *dev_flags, sci_stream_t stream);
+int32_t sci_energy_method(sci_ham_t ham, int64_t n_sel);
+
+/*
  * Batched energy (several systems; the per-block work of sci_energy over tile
  * lists covering every system, a handful of launches in all).  Each item is
  * one sci_energy call (sel strictly ascending, psi, energy required; h_psi and

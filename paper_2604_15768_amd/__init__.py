@@ -25,6 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsci.so")
 
 SCI_OK, SCI_EINVAL, SCI_ECAPACITY, SCI_ENOMEM, SCI_EHIP, SCI_EUNSUPPORTED = range(6)
+ENERGY_AUTO, ENERGY_PAIRS, ENERGY_ENUM = 0, 1, 2
 FLAG_OVERFLOW, FLAG_BAD_DET, FLAG_UNSORTED = 0x1, 0x2, 0x4
 MAX_WORDS = 2
 MAX_ORB = 64
@@ -58,6 +59,10 @@ _lib.sci_energy_workspace_bytes.argtypes = [_i64]
 _lib.sci_energy_workspace_bytes.restype = _sz
 _lib.sci_energy.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _P, _sz, _P, _P]
 _lib.sci_energy.restype = _i32
+_lib.sci_energy_ex.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _i32, _P, _sz, _P, _P]
+_lib.sci_energy_ex.restype = _i32
+_lib.sci_energy_method.argtypes = [_P, _i64]
+_lib.sci_energy_method.restype = _i32
 _lib.sci_stream_workspace_bytes.argtypes = [_P, _i64]
 _lib.sci_stream_workspace_bytes.restype = _sz
 _lib.sci_stream_dedup.argtypes = [_P, _P, _i64, _i64, _i64, _i64, _P, _P, _P, _P, _i64, _P,
@@ -275,8 +280,13 @@ def sci_dedup_merge(n_words, cand, n_cand, set_in, n_set_in, set_out, n_set_out,
            "sci_dedup_merge")
 
 
+def sci_energy_method(ham: Ham, n_sel: int) -> int:
+    """The membership method sci_energy picks for n_sel determinants (ENERGY_PAIRS / ENERGY_ENUM)."""
+    return int(_lib.sci_energy_method(ham.handle, n_sel))
+
+
 def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, workspace_bytes, dev_flags,
-               stream=None):
+               stream=None, method=ENERGY_AUTO):
     dev = sel.device
     _check_keys(sel, ham.W, n_sel, "sel")
     _check_vec(psi, torch.float64, n_sel, "psi", dev)
@@ -285,8 +295,9 @@ def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, worksp
     _check_vec(grad, torch.float64, n_sel, "grad", dev)
     _check_vec(workspace, torch.uint8, workspace_bytes, "workspace", dev)
     _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
-    _check(_lib.sci_energy(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
-                           _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)), "sci_energy")
+    _check(_lib.sci_energy_ex(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
+                              int(method), _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)),
+           "sci_energy")
 
 
 def sci_stream_workspace_bytes(ham: Ham, chunk: int) -> int:
@@ -389,7 +400,7 @@ def dedup_merge(cand: torch.Tensor, set_in: torch.Tensor, n_words: int, want_nov
 
 
 def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_grad=True, flags=None,
-           workspace=None):
+           workspace=None, method=ENERGY_AUTO):
     _need(sel.dim() == 2 and psi.dim() == 1 and psi.shape[0] == sel.shape[0],
           "energy: expected sel (n, W) and psi (n,)")
     dev = sel.device
@@ -402,7 +413,7 @@ def energy(ham: Ham, sel: torch.Tensor, psi: torch.Tensor, want_hpsi=True, want_
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     if flags is None:
         flags = new_flags(dev)
-    sci_energy(ham, sel, n, psi, e, hp, g, workspace, workspace.numel(), flags)
+    sci_energy(ham, sel, n, psi, e, hp, g, workspace, workspace.numel(), flags, method=method)
     return e, hp, g, flags
 
 

@@ -4,15 +4,21 @@
 //   (H psi)_i = H_ii psi_i + sum_{j in S, j != i} H_ij psi_j
 //   E = psi.(H psi) / psi.psi,   g_i = 2((H psi)_i - E psi_i) / psi.psi
 //
-// Membership of j in C_i is decided by pair screening: H_ij can be non-zero
-// only when D_i XOR D_j has two or four set bits (at most two electrons moved,
-// paper section 2.1).  A workgroup owns 256 rows (one per lane) and streams every
-// determinant of S through LDS in tiles; all lanes read the same LDS entry at
-// a time (broadcast), so the screening is one XOR + popcount per pair.  For a
-// connected pair the lane rebuilds the excitation from the XOR bits and reads
-// the same integral tables the generation kernel uses; H_ij is never stored.
-// Row sums run in ascending j, block sums in a fixed tree, so repeated calls
-// are bit-identical.
+// Membership of j in C_i is decided one of two ways, picked per shape:
+//   pair screening  H_ij can be non-zero only when D_i XOR D_j has two or four
+//       set bits (at most two electrons moved, paper section 2.1).  A workgroup
+//       owns 256 rows (one per lane) and streams every determinant of S through
+//       LDS in tiles; all lanes read the same LDS entry at a time (broadcast), so
+//       the screening is one XOR + popcount per pair: |S|^2 tests.
+//   enumeration     C_i is generated (every single and double of D_i) and each
+//       determinant searched in the sorted S (the paper's search of configurations
+//       in a sorted set, section 4.3): |S| N_c searches, a win when N_c is small
+//       against |S|.
+// For a connected pair the lane rebuilds the excitation from the XOR bits and
+// reads the same integral tables the generation kernel uses; H_ij is never
+// stored.  Row sums run in a fixed order (ascending j for pair screening, the
+// excitation order for enumeration), block sums in a fixed tree, so repeated
+// calls are bit-identical.
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -38,6 +44,10 @@ struct EnergyArgs {
     double *energy;    // [1]
     double *grad;      // nullable [n_sel]
     uint32_t *flags;
+    // enumeration only: empty orbitals per spin and the lexicographic pairs (i | j << 8)
+    // of v_alpha and v_beta items
+    int va, vb;
+    const uint16_t *vpairs[2];
 };
 
 template <int W>
@@ -277,6 +287,147 @@ __global__ __launch_bounds__(kRowThreads) void hpsi_kernel(EnergyArgs a) {
     hpsi_tile<W>(a, blockIdx.x, blockIdx.y, gridDim.y, S);
 }
 
+// ---------------------------------------------------------------------------
+// off-diagonal row sums by enumeration of C_i and search in the sorted S
+// ---------------------------------------------------------------------------
+
+constexpr int kEnumThreads = 256;
+constexpr int kEnumTop = 1024;  // every R-th key of S held in LDS (all of S when it fits)
+
+// Position of k in the ascending S[0, n), or -1: the top level (top[t] = S[t R]) is
+// searched in LDS, then the R-key block it names in S.
+template <int W>
+__device__ __forceinline__ int64_t find_sorted(const uint64_t *S, int64_t n, const Key<W> *top, int nt, int64_t R,
+                                               const Key<W> &k) {
+    int lo = 0, hi = nt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (key_less<W>(k, top[mid])) hi = mid;
+        else lo = mid + 1;
+    }
+    if (lo == 0) return -1;  // below S[0]
+    int64_t b = (int64_t)(lo - 1) * R, e = b + R < n ? b + R : n;
+    while (b < e) {
+        const int64_t mid = b + ((e - b) >> 1);
+        const Key<W> m = load_key<W>(S, mid);
+        if (key_less<W>(m, k)) b = mid + 1;
+        else if (key_less<W>(k, m)) e = mid;
+        else return mid;
+    }
+    return -1;
+}
+
+struct EnumLds {
+    uint8_t occ[2][64];
+    uint8_t vir[2][64];
+    int bad;
+    double wsum[kEnumThreads / kWave];
+};
+
+// A persistent grid over the rows: per row i, every excitation of D_i (rows of
+// excitations sharing their holes, lanes over the particles) is searched in S; a
+// member j adds <D_i|H|D_j> psi_j.  The row's sum goes to partial_rows[0][i].
+template <int W>
+__global__ __launch_bounds__(kEnumThreads) void hpsi_enum_kernel(EnergyArgs a) {
+    __shared__ Key<W> top[kEnumTop];
+    __shared__ EnumLds L;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t nS = a.n_sel;
+    const int64_t R = ceil_div_dev(nS, kEnumTop);
+    const int nt = (int)ceil_div_dev(nS, R);
+    for (int t = tid; t < nt; t += kEnumThreads) top[t] = load_key<W>(a.sel, (int64_t)t * R);
+    const int n = a.n;
+    const int pa = a.na * (a.na - 1) / 2, pb = a.nb * (a.nb - 1) / 2;
+    const int g1 = a.na, g2 = g1 + a.nb, g3 = g2 + pa, g4 = g3 + pb, n_rows = g4 + a.na * a.nb;
+    const int pva = a.va * (a.va - 1) / 2, pvb = a.vb * (a.vb - 1) / 2;
+    for (int64_t i = blockIdx.x; i < nS; i += gridDim.x) {
+        __syncthreads();  // the previous row is done with L (and top is loaded)
+        const Key<W> di = load_key<W>(a.sel, i);
+        if (tid == 0) {
+            int na, nb;
+            spin_popc<W>(di, n, na, nb);
+            L.bad = (na != a.na || nb != a.nb || key_popc<W>(di) != na + nb) ? 1 : 0;
+            if (L.bad) atomicOr(a.flags, SCI_FLAG_BAD_DET);
+            if (i + 1 < nS && !key_less<W>(di, load_key<W>(a.sel, i + 1))) atomicOr(a.flags, SCI_FLAG_UNSORTED);
+        }
+        if (tid < 2 * n) {
+            const int sg = tid >= n ? 1 : 0;
+            const int p = tid - sg * n;
+            const int below = key_popc_below<W>(di, tid) - (sg ? key_popc_below<W>(di, n) : 0);
+            uint64_t word = di.w[0];
+#pragma unroll
+            for (int j = 1; j < W; ++j) word = ((tid >> 6) == j) ? di.w[j] : word;
+            if ((word >> (tid & 63)) & 1ull) {
+                if (below < 64) L.occ[sg][below] = (uint8_t)p;
+            } else if (p - below >= 0 && p - below < 64) {
+                L.vir[sg][p - below] = (uint8_t)p;
+            }
+        }
+        __syncthreads();
+        double acc = 0.0;
+        if (!L.bad) {
+            for (int g = wave; g < n_rows; g += kEnumThreads / kWave) {
+                Key<W> rk = di;
+                int R_len, sg = 0, kind;  // kind 0 single, 1 same-spin double, 2 mixed double
+                if (g < g2) {
+                    sg = g < g1 ? 0 : 1;
+                    key_flip<W>(rk, L.occ[sg][sg ? g - g1 : g] + sg * n);
+                    R_len = sg ? a.vb : a.va;
+                    kind = 0;
+                } else if (g < g4) {
+                    sg = g < g3 ? 0 : 1;
+                    // hole pair o of this spin, lexicographic: o -> (x < y)
+                    int o = sg ? g - g3 : g - g2, x = 0, m = sg ? a.nb : a.na;
+                    while (o >= m - 1 - x) {
+                        o -= m - 1 - x;
+                        ++x;
+                    }
+                    key_flip<W>(rk, L.occ[sg][x] + sg * n);
+                    key_flip<W>(rk, L.occ[sg][x + 1 + o] + sg * n);
+                    R_len = sg ? pvb : pva;
+                    kind = 1;
+                } else {
+                    const int o = g - g4, ip = o / a.nb, iq = o - ip * a.nb;
+                    key_flip<W>(rk, L.occ[0][ip]);
+                    key_flip<W>(rk, L.occ[1][iq] + n);
+                    R_len = a.va * a.vb;
+                    kind = 2;
+                }
+                for (int t = lane; t < R_len; t += kWave) {
+                    Key<W> key = rk;
+                    if (kind == 0) {
+                        key_flip<W>(key, L.vir[sg][t] + sg * n);
+                    } else if (kind == 1) {
+                        const uint32_t pv = a.vpairs[sg][t];
+                        key_flip<W>(key, L.vir[sg][pv & 0xff] + sg * n);
+                        key_flip<W>(key, L.vir[sg][pv >> 8] + sg * n);
+                    } else {
+                        const int ia = t / a.vb, ib = t - ia * a.vb;
+                        key_flip<W>(key, L.vir[0][ia]);
+                        key_flip<W>(key, L.vir[1][ib] + n);
+                    }
+                    const int64_t j = find_sorted<W>(a.sel, nS, top, nt, R, key);
+                    if (j >= 0) {
+                        Key<W> x;
+#pragma unroll
+                        for (int q = 0; q < W; ++q) x.w[q] = di.w[q] ^ key.w[q];
+                        acc += offdiag_elem<W>(a, di, key, x, kind == 0 ? 2 : 4) * a.psi[j];
+                    }
+                }
+            }
+        }
+        // fixed-order block sum: a butterfly inside each wave, then the waves in order
+        for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) L.wsum[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kEnumThreads / kWave; ++w) t += L.wsum[w];
+            a.partial_rows[i] = t;
+        }
+    }
+}
+
 // (H psi)_i = H_ii psi_i + the column-block partial sums in block order
 template <int W>
 __device__ __forceinline__ void hpsi_finish_rows(const EnergyArgs &a, int64_t rb, int n_col) {
@@ -384,6 +535,10 @@ constexpr size_t energy_ws(int64_t n_sel) {
 static EnergyArgs energy_args(const HamDev &d, const uint64_t *sel, int64_t n_sel, const double *psi, double *energy,
                               double *h_psi, double *grad, char *ws, uint32_t *dev_flags) {
     EnergyArgs a;
+    a.va = d.v_alpha;
+    a.vb = d.v_beta;
+    a.vpairs[0] = d.pairs[2];
+    a.vpairs[1] = d.pairs[3];
     a.n = d.n_orb;
     a.na = d.n_alpha;
     a.nb = d.n_beta;
@@ -410,10 +565,20 @@ static EnergyArgs energy_args(const HamDev &d, const uint64_t *sel, int64_t n_se
     return a;
 }
 
+// Membership by enumeration when |S| exceeds N_c by this factor (pair screening
+// tests |S|^2 pairs at about one XOR + popcount each; enumeration builds |S| N_c
+// determinants and searches each in S, some tens of operations each).
+constexpr int64_t kEnumRatio = 64;
+
+static int pick_method(const HamDev &d, int64_t n_sel, int32_t method) {
+    if (method == SCI_ENERGY_PAIRS || method == SCI_ENERGY_ENUM) return method;
+    return d.n_coupled * kEnumRatio < n_sel ? SCI_ENERGY_ENUM : SCI_ENERGY_PAIRS;
+}
+
 // Every kernel of one energy evaluation, in order, on `st`.  `timed` launches go through
 // the per-launch profiler (which may create events); the allocation-free entry point
 // launches untimed.
-static int32_t energy_launch(int W, const EnergyArgs &a, hipStream_t st, bool timed) {
+static int32_t energy_launch(int W, const EnergyArgs &a, hipStream_t st, bool timed, int method) {
 #define SCI_ELAUNCH(kern, ...)                          \
     do {                                                \
         if (timed) SCI_LAUNCH(kern, __VA_ARGS__);       \
@@ -421,13 +586,26 @@ static int32_t energy_launch(int W, const EnergyArgs &a, hipStream_t st, bool ti
     } while (0)
     const int64_t n_sel = a.n_sel;
     const int64_t row_blocks = ceil_div(n_sel, kRowThreads);
-    const int nc = col_split(n_sel);
-    if (W == 1) {
-        SCI_ELAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
-        SCI_ELAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+    if (method == SCI_ENERGY_ENUM) {
+        int dev = 0, n_cu = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        const unsigned g = (unsigned)std::min<int64_t>(n_sel, (int64_t)std::max(n_cu, 1) * 8);
+        if (W == 1) {
+            SCI_ELAUNCH(hpsi_enum_kernel<1>, dim3(g), dim3(kEnumThreads), 0, st, a);
+            SCI_ELAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, 1);
+        } else {
+            SCI_ELAUNCH(hpsi_enum_kernel<2>, dim3(g), dim3(kEnumThreads), 0, st, a);
+            SCI_ELAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, 1);
+        }
     } else {
-        SCI_ELAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
-        SCI_ELAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+        const int nc = col_split(n_sel);
+        if (W == 1) {
+            SCI_ELAUNCH(hpsi_kernel<1>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+            SCI_ELAUNCH(hpsi_finish_kernel<1>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+        } else {
+            SCI_ELAUNCH(hpsi_kernel<2>, dim3((unsigned)row_blocks, nc), dim3(kRowThreads), 0, st, a);
+            SCI_ELAUNCH(hpsi_finish_kernel<2>, dim3((unsigned)row_blocks), dim3(kRowThreads), 0, st, a, nc);
+        }
     }
     SCI_HIP_TRY(hipGetLastError());
     const int64_t nb = reduce_blocks(n_sel);
@@ -462,17 +640,31 @@ extern "C" size_t sci_energy_workspace_bytes(int64_t n_sel) {
     return energy_ws(n_sel);
 }
 
-extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
-                              double *energy, double *h_psi, double *grad, void *workspace,
-                              size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
+extern "C" int32_t sci_energy_method(sci_ham_t ham, int64_t n_sel) {
+    if (!ham || n_sel < 1) return -1;
+    return pick_method(ham->dev, n_sel, SCI_ENERGY_AUTO);
+}
+
+extern "C" int32_t sci_energy_ex(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                                 double *energy, double *h_psi, double *grad, int32_t method, void *workspace,
+                                 size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
     set_error("");
     int32_t rc = energy_check("sci_energy", ham, sel, n_sel, psi, energy, dev_flags);
     if (rc != SCI_OK) return rc;
+    if (method < SCI_ENERGY_AUTO || method > SCI_ENERGY_ENUM)
+        return fail(SCI_EINVAL, "sci_energy: unknown method %d", method);
     if (!workspace) return fail(SCI_EINVAL, "sci_energy: NULL pointer argument");
     if (workspace_bytes < energy_ws(n_sel))
         return fail(SCI_ECAPACITY, "sci_energy: workspace %zu < %zu bytes", workspace_bytes, energy_ws(n_sel));
     const EnergyArgs a = energy_args(ham->dev, sel, n_sel, psi, energy, h_psi, grad, (char *)workspace, dev_flags);
-    return energy_launch(ham->dev.W, a, (hipStream_t)stream, true);
+    return energy_launch(ham->dev.W, a, (hipStream_t)stream, true, pick_method(ham->dev, n_sel, method));
+}
+
+extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                              double *energy, double *h_psi, double *grad, void *workspace,
+                              size_t workspace_bytes, uint32_t *dev_flags, sci_stream_t stream) {
+    return sci_energy_ex(ham, sel, n_sel, psi, energy, h_psi, grad, SCI_ENERGY_AUTO, workspace, workspace_bytes,
+                         dev_flags, stream);
 }
 
 // ---------------------------------------------------------------------------

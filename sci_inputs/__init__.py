@@ -303,7 +303,7 @@ def _select_levels_enumerated(rng, n_orb, n_alpha, n_beta, n_sel, max_level):
     x = full ^ ref_w
     moved = np.zeros(full.shape[0], dtype=np.int64)
     for j in range(W):
-        moved += np.unpackbits(x[:, j:j + 1].view(np.uint8), axis=1).sum(axis=1)
+        moved += np.unpackbits(x[:, j:j + 1].view(np.uint8), axis=1).sum(axis=1).astype(np.int64)
     level = moved // 2
     pool = np.flatnonzero((level >= 1) & (level <= max_level))
     pick = rng.choice(pool.shape[0], size=n_sel - 1, replace=False)

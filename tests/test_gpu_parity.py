@@ -340,14 +340,23 @@ def test_dedup_flags():
 # energy
 # ---------------------------------------------------------------------------
 
-def test_energy_tiny_matches_oracle():
+METHODS = ["pairs", "enum"]
+
+
+def _method(sci, name):
+    return {"pairs": sci.ENERGY_PAIRS, "enum": sci.ENERGY_ENUM}[name]
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_energy_tiny_matches_oracle(method):
     import torch
     sci = require_gpu()
     s = system("tiny")
     h = ham("tiny")
     sel = sci.keys_to_device(s.dets)
     psi = torch.from_numpy(s.psi).cuda()
-    e, hp, g, flags = sci.energy(h, sel, psi)
+    m = _method(sci, method)
+    e, hp, g, flags = sci.energy(h, sel, psi, method=m)
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "energy") == 0
     oe, ohp, og = oracle.energy(s.n_orb, s.n_alpha, s.n_beta, s.h1, s.eri, s.dets, s.psi)
@@ -356,12 +365,13 @@ def test_energy_tiny_matches_oracle():
     assert np.max(np.abs(hp.cpu().numpy() - ohp)) <= H_TOL * 10
     assert np.max(np.abs(g.cpu().numpy() - og)) <= G_TOL
     # bit-reproducible
-    e2, hp2, g2, _ = sci.energy(h, sel, psi)
+    e2, hp2, g2, _ = sci.energy(h, sel, psi, method=m)
     torch.cuda.synchronize()
     assert e2.item() == e.item() and torch.equal(hp2, hp) and torch.equal(g2, g)
 
 
-def test_energy_full_space_eigenvector():
+@pytest.mark.parametrize("method", METHODS)
+def test_energy_full_space_eigenvector(method):
     import torch
     sci = require_gpu()
     n, na, nb = 6, 3, 2
@@ -372,22 +382,24 @@ def test_energy_full_space_eigenvector():
     hd = oracle.dense_h_sc(n, na, nb, h1, eri, basis)
     w, v = np.linalg.eigh(hd)
     h = sci.Ham(n, na, nb, h1, eri)
-    e, hp, g, flags = sci.energy(h, sci.keys_to_device(basis), torch.from_numpy(v[:, 0].copy()).cuda())
+    e, hp, g, flags = sci.energy(h, sci.keys_to_device(basis), torch.from_numpy(v[:, 0].copy()).cuda(),
+                                 method=_method(sci, method))
     torch.cuda.synchronize()
     assert abs(e.item() - w[0]) <= E_TOL
     assert np.max(np.abs(g.cpu().numpy())) <= 1e-9
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("name,n_rows", [("medium", 24), ("large", 8)])
-def test_energy_sampled_rows(name, n_rows):
+def test_energy_sampled_rows(name, n_rows, method):
     import torch
     sci = require_gpu()
     s = system(name)
     h = ham(name)
     sel = sci.keys_to_device(s.dets)
     psi = torch.from_numpy(s.psi).cuda()
-    say(f"energy {name}: n_sel={s.dets.shape[0]}")
-    e, hp, g, flags = sci.energy(h, sel, psi)
+    say(f"energy {name} ({method}): n_sel={s.dets.shape[0]}")
+    e, hp, g, flags = sci.energy(h, sel, psi, method=_method(sci, method))
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "energy") == 0
     rows = pick_sources(s.dets.shape[0], n_rows, 21)
@@ -405,15 +417,62 @@ def test_energy_sampled_rows(name, n_rows):
     assert abs(float(np.dot(s.psi, gg))) <= 1e-9
 
 
-def test_energy_flags():
+@pytest.mark.parametrize("method", METHODS)
+def test_energy_flags(method):
     import torch
     sci = require_gpu()
     s = system("tiny")
     h = ham("tiny")
     sel = sci.keys_to_device(s.dets[::-1].copy())
-    _, _, _, flags = sci.energy(h, sel, torch.from_numpy(s.psi).cuda())
+    _, _, _, flags = sci.energy(h, sel, torch.from_numpy(s.psi).cuda(), method=_method(sci, method))
     torch.cuda.synchronize()
     assert sci.check_flags(flags, "energy", allow=sci.FLAG_UNSORTED) & sci.FLAG_UNSORTED
+    bad = s.dets.copy()
+    bad[3, 0] ^= np.uint64(1) << np.uint64(2 * s.n_orb + 1)  # a bit beyond 2 n_orb
+    _, _, _, flags = sci.energy(h, sci.keys_to_device(bad), torch.from_numpy(s.psi).cuda(),
+                                method=_method(sci, method))
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy", allow=sci.FLAG_BAD_DET | sci.FLAG_UNSORTED) & sci.FLAG_BAD_DET
+
+
+def test_energy_methods_agree_and_auto_choice():
+    """Both membership methods give the same H psi (to rounding) on the medium system and
+    on a small-orbital system (N_c = 804) of the kind the batched workload holds, and the
+    automatic choice gives one of them."""
+    import torch
+    sci = require_gpu()
+    s = system("medium")
+    h = ham("medium")
+    sel = sci.keys_to_device(s.dets)
+    psi = torch.from_numpy(s.psi).cuda()
+    e1, hp1, g1, f1 = sci.energy(h, sel, psi, method=sci.ENERGY_PAIRS)
+    e2, hp2, g2, f2 = sci.energy(h, sel, psi, method=sci.ENERGY_ENUM)
+    torch.cuda.synchronize()
+    assert sci.check_flags(f1, "pairs") == 0 and sci.check_flags(f2, "enum") == 0
+    assert abs(e1.item() - e2.item()) <= E_TOL
+    assert float((hp1 - hp2).abs().max().item()) <= 1e-11
+    assert float((g1 - g2).abs().max().item()) <= G_TOL
+    assert sci.sci_energy_method(h, s.dets.shape[0]) == sci.ENERGY_PAIRS  # N_c = 25,137 >> |S| / 64
+    # a small-orbital system of the batched workload: N_c = 804 for n_orb = 10, 4a+4b
+    wl = si.small_workload(10, 4, 4, n_sel=17_000, selection="levels")
+    sm = si.make_system(wl)
+    hs = sci.Ham(sm.n_orb, sm.n_alpha, sm.n_beta, sm.h1, sm.eri)
+    sels = sci.keys_to_device(sm.dets)
+    psis = torch.from_numpy(sm.psi).cuda()
+    auto = sci.sci_energy_method(hs, sm.dets.shape[0])
+    say(f"  small system: n_sel={sm.dets.shape[0]}, N_c={hs.n_coupled}, auto method {auto}")
+    assert auto in (sci.ENERGY_PAIRS, sci.ENERGY_ENUM)
+    ea, hpa, _, fa = sci.energy(hs, sels, psis, method=sci.ENERGY_ENUM)
+    ep, hpp, _, fp = sci.energy(hs, sels, psis, method=sci.ENERGY_PAIRS)
+    e0, hp0, _, f0 = sci.energy(hs, sels, psis)
+    torch.cuda.synchronize()
+    assert sci.check_flags(fa, "enum") == 0 and sci.check_flags(fp, "pairs") == 0 and sci.check_flags(f0, "auto") == 0
+    assert abs(ea.item() - ep.item()) <= E_TOL
+    assert float((hpa - hpp).abs().max().item()) <= 1e-11
+    assert torch.equal(hp0, hpa if auto == sci.ENERGY_ENUM else hpp)
+    rows = pick_sources(sm.dets.shape[0], 16, 8)
+    ohp = oracle.hpsi_rows(sm.n_orb, sm.n_alpha, sm.n_beta, sm.h1, sm.eri, sm.dets, sm.psi, rows)
+    assert np.max(np.abs(hpa.cpu().numpy()[rows] - ohp)) <= 1e-11
 
 
 @pytest.mark.parametrize("W", [1, 2])
