@@ -239,7 +239,7 @@ int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const doub
  *                     searched in the sorted S.  |S| N_c searches against |S|^2
  *                     tests: the faster one when N_c is small against |S|.
  *   SCI_ENERGY_AUTO   the method a cost model picks for this shape:
- *                     enumeration when N_c * 64 < n_sel, else pair screening
+ *                     enumeration when N_c * 8 < n_sel, else pair screening
  *                     (sci_energy always uses it; sci_energy_method reports it).
  * sci_energy_ex is sci_energy with the method given; sci_energy_method returns
  * the method SCI_ENERGY_AUTO picks for n_sel determinants of this handle (-1 for

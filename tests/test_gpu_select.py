@@ -46,8 +46,8 @@ def test_inverse_map_matches_oracle(W, n_set, n_cand, kind):
     want = oracle.inverse_map(W, u, cand)
     got = idx.cpu().numpy()
     assert np.array_equal(got, want)
-    if n_set:
-        assert (got >= 0).sum() >= n_cand // 2 and (got < 0).any()
+    if n_set:  # the two boundary keys may have replaced members
+        assert (got >= 0).sum() >= n_cand // 2 - 2 and (got < 0).any()
 
 
 def test_inverse_map_of_generated_candidates():

@@ -23,6 +23,8 @@ SLICE = 1 << 30    # boolean selection works on at most 2^31 - 1 elements at a t
 
 
 def _free():
+    import gc
+    gc.collect()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
@@ -170,28 +172,66 @@ def test_large_streamed_minibatch_exact_ranges():
                 kc = k[c:c + SLICE]
                 ids = torch.searchsorted(hb, kc[:, 1].contiguous(), right=True)
                 for r in group:
-                    parts[r].append(kc[ids == r])
+                    # unique per chunk already: a range's candidates over all chunks can
+                    # exceed one sort's 2^31 - 1 elements, their distinct keys cannot
+                    sel_r = kc[ids == r]
+                    w1, w0 = _rows_order(sel_r[:, 1], sel_r[:, 0])
+                    parts[r].append(_sort_unique_rows(torch.stack([w1, w0], dim=1)))
+                    del sel_r, w1, w0
                 del ids
             del k
             _free()
         for r in group:
-            parts[r].append(sel[sel_ids == r])
+            s_r = sel[sel_ids == r]
+            w1, w0 = _rows_order(s_r[:, 1], s_r[:, 0])
+            parts[r].append(torch.stack([w1, w0], dim=1))
             cand = torch.cat(parts.pop(r))
             got_n = cand.shape[0]
-            w1, w0 = _rows_order(cand[:, 1], cand[:, 0])
-            del cand
-            expect = _sort_unique_rows(torch.stack([w1, w0], dim=1))
-            del w1, w0
+            expect = _sort_unique_rows(cand)
+            del cand, w1, w0, s_r
             i, j = slices[r]
             u1, u0 = _rows_order(union[i:j, 1], union[i:j, 0])
             assert torch.equal(expect, torch.stack([u1, u0], dim=1)), f"union differs in range {r} [{i}, {j})"
             checked += expect.shape[0]
-            say(f"  range {r} [{i}, {j}): {j - i} keys exact from {got_n} candidates")
+            say(f"  range {r} [{i}, {j}): {j - i} keys exact from {got_n} per-chunk distinct candidates")
             del expect, u1, u0
             _free()
     assert checked == n, f"ranges hold {checked} unique keys, the union {n}"
     say(f"  all {n} union keys checked exactly in {n_ranges} ranges")
-    del union
+    _free()
+    # reverse index at this size: a hash table would take sci_index_bytes (2^33 slots of
+    # 32 bytes, 275 GB), so the index is of the sorted kind (every 256th key sampled)
+    n_dev = torch.tensor([n], dtype=torch.int64, device="cuda")
+    table_bytes = sci.sci_index_bytes(2, n)
+    index, fl = sci.build_index(union, n_dev, n, 2)
+    assert sci.index_kind(index) == "sorted" and table_bytes > 2 * 10**11
+    say(f"  reverse index: sorted kind, {index.numel()} bytes (a table would take {table_bytes})")
+    # every candidate of the first chunk is found, at a position holding its key
+    k, _, _, _, _ = sci.gen_coupled(h, dets, exc_begin=0, exc_end=chunk)
+    idx = sci.inverse_map(index, k, 2)
+    torch.cuda.synchronize()
+    assert sci.check_flags(fl, "index") == 0
+    assert bool((idx >= 0).all()), "a generated candidate is missing from the index"
+    for c in range(0, chunk, SLICE // 4):
+        assert torch.equal(union[idx[c:c + SLICE // 4]], k[c:c + SLICE // 4])
+    del k, idx
+    _free()
+    # against the oracle on one range's slice of the union: members at random positions
+    # and the same keys with their lowest bit flipped (same top word, so same range)
+    i, j = slices[n_ranges // 2]
+    rng = np.random.Generator(np.random.PCG64(2604157690))
+    pos = torch.from_numpy(rng.integers(i, j, size=500_000)).cuda()
+    members = union[pos]
+    flipped = members.clone()
+    flipped[:, 0] ^= 1
+    cand = torch.cat([members, flipped])
+    got = sci.inverse_map(index, cand, 2).cpu().numpy()
+    u_slice = sci.keys_to_host(union[i:j])
+    want = oracle.inverse_map(2, u_slice, sci.keys_to_host(cand))
+    want = np.where(want >= 0, want + i, -1)
+    assert np.array_equal(got, want), "sorted reverse index differs from the oracle"
+    say(f"  1e6 lookups in [{i}, {j}) equal the oracle ({int((want >= 0).sum())} found)")
+    del union, index, u_slice
     _free()
 
 
