@@ -19,7 +19,8 @@ per-kernel times come from the library's own event pairs around each launch
 describes the kernel with the largest share of the step against its
 algorithmic bytes (defined per kernel below, from per-chunk set sizes measured
 in an untimed pass before the timed steps); `cpu_baseline` times the CPU oracle
-on a bounded sample of the same workload.  Extras (same line) cover the medium
+on a bounded sample of the same workload.  Extras (same line) cover the whole
+large selected space streamed into one set (7.2e10 candidates), the medium
 workload's full step, screened generation, the reverse index and top-K, energy
 and autograd timings, and the batched workload.
 
@@ -62,8 +63,8 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="a run for counter collection: no size pass, no extras, no CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement")
-    ap.add_argument("--extras", default="medium,select,screened,energy,batch",
-                    help="comma list of extras (medium, select, screened, energy, batch)")
+    ap.add_argument("--extras", default="whole,medium,select,screened,energy,batch",
+                    help="comma list of extras (whole, medium, select, screened, energy, batch)")
     ap.add_argument("--large-sources", type=int, default=32768)
     ap.add_argument("--large-chunk", type=int, default=1 << 30,
                     help="pool chunk in candidates (0: time 2^28, 2^29, 2^30 once each and keep the fastest)")
@@ -357,17 +358,16 @@ def large_algo(sizes, n_src, W):
       gen_kernel      every candidate's key + H_ij written, every source read once
       hist_kernel     every candidate key read (one level)
       scatter_kernel  every candidate key read and written (one level)
-      bucket_kernel   chunk keys read, the chunk's distinct keys written, and the running
-                      set's keys read once (the union count needs each of them compared)
-      emit_kernel     distinct chunk keys + running set read, the new set written
+      bucket_kernel   chunk keys read, the running set's keys read once (each is compared
+                      with the chunk's distinct keys), the distinct keys the set lacks written
+      emit_kernel     those keys + the running set read, the new set written
     Others (splitters, scans, oversized units) have no definition here."""
     kb = 8 * W
     n = sum(s["n"] for s in sizes)
-    u = sum(s["u"] for s in sizes)
     m0 = sum(s["m0"] for s in sizes)
     m1 = sum(s["m1"] for s in sizes)
     table = {"gen_kernel": n * (kb + 8) + n_src * kb, "hist_kernel": n * kb, "scatter_kernel": 2 * n * kb,
-             "bucket_kernel": (n + u + m0) * kb, "emit_kernel": (u + m0 + m1) * kb}
+             "bucket_kernel": (n + m0 + (m1 - m0)) * kb, "emit_kernel": ((m1 - m0) + m0 + m1) * kb}
     return lambda name: table.get(family(name))
 
 
@@ -542,8 +542,9 @@ def medium_step(args, torch, sci, si, copy_gbps):
     kb = 8 * W
     gen_bytes = n_cand * (kb + 8) + n_sel * kb
     dedup_lb = 2 * n_cand * kb
+    n_novel = n_union - n_sel
     table = {"gen_kernel": gen_bytes, "hist_kernel": n_cand * kb, "scatter_kernel": 2 * n_cand * kb,
-             "bucket_kernel": (n_cand + n_distinct + n_sel) * kb, "emit_kernel": (n_distinct + n_sel + n_union) * kb}
+             "bucket_kernel": (n_cand + n_sel + n_novel) * kb, "emit_kernel": (n_novel + n_sel + n_union) * kb}
     algo = lambda name: table.get(family(name))
     res = {
         "workload": f"{wl.name}: n_orb={wl.n_orb} {wl.n_alpha}a+{wl.n_beta}b rank={wl.rank} n_sel={n_sel} W={W}; "
@@ -642,6 +643,59 @@ def select_extras(torch, sci, keys, n_cand, union, n_union_dev, n_union, sel, n_
     sci.check_flags(flags, "topk")
     t_ms = _median_ms(run, 3, torch)
     out["topk"] = {"n": nn, "k": K, "ms": t_ms, "entries_per_s": nn / (t_ms / 1000.0), "n_selected": int(n_out.item())}
+    return out
+
+
+def whole_extras(args, torch, sci, ham, sel):
+    """All selected determinants of the large workload as sources (7.2e10 candidates)
+    streamed through the device pool into one set on one GPU (sci_stream_dedup): time
+    of one pass, union size, peak device memory."""
+    dev = sel.device
+    W = ham.W
+    n_sel = sel.shape[0]
+    total = n_sel * ham.n_coupled
+    chunk = args.large_chunk if args.large_chunk > 0 else 1 << 30
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    free_bytes = torch.cuda.mem_get_info(dev)[0]
+    cap = int(min(total + n_sel, (free_bytes - (4 << 30)) // (2 * W * 8)))
+    set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
+    set_b = torch.empty_like(set_a)
+    n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    flags = sci.new_flags(dev)
+    cur = torch.cuda.current_stream()
+    dd = torch.cuda.Stream()
+    fb = [False]
+
+    def run():
+        fb[0] = sci.sci_stream_dedup(ham, sel, n_sel, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out,
+                                     ws, ws.numel(), flags, cur, dd)
+        cur.wait_stream(dd)
+
+    t_ms = _median_ms(run, 1, torch)
+    sci.check_flags(flags, "whole selected space")
+    n_union = int(n_out.item())
+    res = set_b if fb[0] else set_a
+    # strictly ascending at full size, checked on the device in slices
+    ok = True
+    for a0 in range(0, n_union - 1, 1 << 30):
+        b0 = min(a0 + (1 << 30) + 1, n_union)
+        hi, lo = res[a0:b0, 1], res[a0:b0, 0] ^ (-(1 << 63))
+        up = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))
+        ok = ok and bool(up.all())
+        del hi, lo, up
+    out = {"workload": f"large: all {n_sel} selected determinants as sources ({total} candidates) streamed in "
+                       f"chunks of {chunk} into one set (sci_stream_dedup), one pass",
+           "n_candidates": total, "chunk": chunk, "n_chunks": -(-total // chunk), "ms": t_ms,
+           "candidates_per_s": total / (t_ms / 1000.0), "n_unique_union": n_union, "union_ascending": ok,
+           "redundancy": total / n_union, "set_capacity": cap,
+           "device_bytes": {"pool_and_workspace": ws_bytes, "set_buffers": 2 * cap * W * 8,
+                            "peak_allocated": torch.cuda.max_memory_allocated(dev)}}
+    del ws, set_a, set_b, res
+    torch.cuda.empty_cache()
     return out
 
 
@@ -876,6 +930,9 @@ def main():
     if "energy" in extras and ctx_large is not None:
         ham, sel, psi, _ = ctx_large
         result["extras"]["energy_grad_large"] = energy_extras(torch, sci, si, ham, sel, psi)
+    if "whole" in extras and ctx_large is not None:
+        ham, sel, _, _ = ctx_large
+        result["extras"]["large_whole_stream"] = whole_extras(args, torch, sci, ham, sel)
     ctx_large = None
     torch.cuda.empty_cache()
     if extras & {"medium", "select", "screened"}:

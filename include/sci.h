@@ -82,9 +82,10 @@ int64_t sci_n_coupled(int32_t n_orb, int32_t n_alpha, int32_t n_beta);
  * (paper section 4.2, the single/double excitation tables; here the
  * integral slices V_pq[a][b] = (ap|bq) and their antisymmetrised same-spin
  * form).  h1_host, eri_host: host arrays as above.  On success *out owns one
- * device allocation of about (3*n_orb^4 + 2*n_orb^3 + 3*n_orb^2)*8 bytes
+ * device allocation of about (3*n_orb^4 + 2*n_orb^3 + 5*n_orb^2)*8 bytes
  * (the ERI, the two n^4 slice tables, the n^3 Coulomb/exchange row tables,
- * h1, J, K; plus small pair lists) until sci_ham_destroy: 311 MB for n_orb=60.
+ * h1, J, K, the reference determinant's single-excitation elements per spin;
+ * plus small pair lists) until sci_ham_destroy: 311 MB for n_orb=60.
  * The handle is immutable and may be used from several streams at once.
  * Synchronous and stream-free (unlike the compute calls): the integrals are
  * copied with blocking copies, the tables are built on the null stream, and

@@ -14,9 +14,10 @@
 //          followed by run-length unique.  Buckets cover disjoint, ascending
 //          key ranges, so the concatenated unique runs are globally sorted and
 //          equal keys can never straddle two buckets.
-// The sorted unique run is then merged with the running set by merge path,
-// keeping one copy of keys present in both and optionally emitting the keys
-// that were not in the set ("novel").
+// Each unique run then drops the keys the running set already holds in its
+// range (found while the run is in LDS), and what is left ("novel", optionally
+// emitted) is inserted among the set keys: every set key moves by the number of
+// run keys below it, so the merge reads the run and the set range once.
 //
 // Sort vs. hash (paper section 4.1.2): no hash table and no global atomics on
 // keys; the only atomics are LDS counters.  A bucket larger than the LDS
@@ -37,12 +38,15 @@ struct DCfg {
     static constexpr int CAP = (W == 1) ? 3072 : 1536;     // LDS sort capacity (keys)
     static constexpr int K = CAP / kDThreads;              // keys per thread
     static constexpr int CH = CAP / kDWaves;               // keys per wave
-    // mean final bucket size (tail past CAP is rare); two-word keys get three level-2
+    // mean final bucket size (tail past CAP is rare); two-word keys get fewer level-2
     // samples per bucket, a wider spread, so their mean stays further below CAP
     static constexpr int TARGET = (W == 1) ? CAP * 3 / 8 : CAP / 4;
     static constexpr int F1 = 4096;                        // level-1 fan-out bound
     static constexpr int F2 = 512;                         // level-2 fan-out bound
-    static constexpr int OVS2 = CAP / F2;                  // level-2 oversampling (6 W=1, 3 W=2)
+    // level-2 splitters: one workgroup sorts up to SCAP samples per level-1 bucket in
+    // LDS (the whole of a CU's LDS for two-word keys), OVS2 samples per final bucket
+    static constexpr int SCAP = (W == 1) ? 6144 : 4096;
+    static constexpr int OVS2 = SCAP / F2;                 // 12 W=1, 8 W=2
     static constexpr int M1 = 65536;                       // level-1 sample bound
     static constexpr int64_t TILE1 = 131072;               // keys per level-1 tile
     static constexpr int64_t TILE2 = 16384;                // keys per level-2 tile
@@ -143,22 +147,24 @@ __device__ void radix_offsets(RadixLds &R, uint32_t *dtot) {
     for (int w = 0; w < kDWaves; ++w) R.cnt[w][t] += (uint32_t)base;
 }
 
-// Stable LSD radix sort (8-bit digits over bits [0, nbits)) of m <= CAP keys in LDS.
+// Stable LSD radix sort (8-bit digits over bits [0, nbits)) of m <= MAXM keys in LDS.
 // Returns the buffer holding the result (buf or tmp).
-template <int W>
+template <int W, int MAXM = DCfg<W>::CAP>
 __device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, const Key<W> &orkey, RadixLds &R) {
-    using C = DCfg<W>;
+    constexpr int kK = MAXM / kDThreads;   // keys per thread
+    constexpr int kCH = MAXM / kDWaves;    // keys per wave
+    static_assert(MAXM % kDThreads == 0 && MAXM < 65536, "radix sort capacity");
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int shift = 0; shift < nbits; shift += 8) {
         const uint32_t vm = digit_of<W>(orkey, shift);  // bits of this window that vary
         if (vm == 0u) continue;                         // an identity pass
 
         for (int d = lane; d < 256; d += kWave) R.cnt[w][d] = 0;
-        Key<W> kr[C::K];
-        uint32_t meta[C::K];  // local rank | digit << 16
+        Key<W> kr[kK];
+        uint32_t meta[kK];  // local rank | digit << 16
 #pragma unroll
-        for (int k = 0; k < C::K; ++k) {
-            const int pos = w * C::CH + k * kWave + lane;
+        for (int k = 0; k < kK; ++k) {
+            const int pos = w * kCH + k * kWave + lane;
             const bool valid = pos < m;
             Key<W> key;
             if (valid) key = buf[pos];
@@ -179,8 +185,8 @@ __device__ Key<W> *lds_radix_sort(Key<W> *buf, Key<W> *tmp, int m, int nbits, co
         radix_offsets(R, nullptr);
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < C::K; ++k) {
-            const int pos = w * C::CH + k * kWave + lane;
+        for (int k = 0; k < kK; ++k) {
+            const int pos = w * kCH + k * kWave + lane;
             if (pos < m) {
                 const uint32_t d = meta[k] >> 16;
                 tmp[R.cnt[w][d] + (meta[k] & 0xffffu)] = kr[k];
@@ -362,8 +368,8 @@ __device__ __forceinline__ int64_t sample_pos(int64_t start, int64_t size, int64
 template <int W>
 __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     using C = DCfg<W>;
-    __shared__ Key<W> s_buf[C::CAP];
-    __shared__ Key<W> s_tmp[C::CAP];
+    __shared__ Key<W> s_buf[C::SCAP];
+    __shared__ Key<W> s_tmp[C::SCAP];
     __shared__ RadixLds R;
     const int s = blockIdx.x;
     const int64_t start = a.seg_in[s], size = seg_size(a.seg_in, s);
@@ -372,7 +378,7 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     if (threadIdx.x == 0) a.fan[s] = f;
     if (f == 1) return;
     const int64_t M = std::min<int64_t>(size, std::min<int64_t>((int64_t)a.ovs * f, a.max_samples));
-    if (M > C::CAP) return;  // cannot happen: the host sorts larger samples in runs
+    if (M > C::SCAP) return;  // cannot happen: the host sorts larger samples in runs
     uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
     for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
         s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k, M));
@@ -382,7 +388,7 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     __syncthreads();
     Key<W> orkey;
     const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R, &orkey);
-    Key<W> *res = lds_radix_sort<W>(s_buf, s_tmp, (int)M, nbits, orkey, R);
+    Key<W> *res = lds_radix_sort<W, C::SCAP>(s_buf, s_tmp, (int)M, nbits, orkey, R);
     for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
         const int64_t r = ((int64_t)(j + 1) * M) / f;
         store_key<W>(sp, j, res[r]);
@@ -542,18 +548,24 @@ __global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
     const int64_t start = a.seg_in[s] + t * a.tile;
     const int64_t end = std::min<int64_t>(start + a.tile, a.seg_in[s + 1]);
     const uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
-    // splitters padded to FMAX-1 with the all-ones key, which no key is above: every
-    // search below takes exactly log2(FMAX) steps with no bounds checks
-    for (int j = threadIdx.x; j < FMAX - 1; j += kH) {
-        if (j < f - 1) s_spl[j] = load_key<W>(sp, j);
+    constexpr int kSteps = __builtin_ctz(FMAX);
+    // Splitters padded to FMAX-1 with the all-ones key, which no key is above, form a
+    // perfect binary search tree stored level by level (node j at s_spl[j-1], children
+    // 2j and 2j+1): sorted splitter i sits at depth d = kSteps-1-ctz(i+1), position
+    // (i+1) >> (ctz(i+1)+1) in that level.  The lanes of a wave then read one
+    // contiguous level per step instead of entries a power of two apart (which fall
+    // into the same LDS bank), and every search takes exactly log2(FMAX) steps.
+    for (int i = threadIdx.x; i < FMAX - 1; i += kH) {
+        const int z = __builtin_ctz((unsigned)(i + 1));
+        const int j = (1 << (kSteps - 1 - z)) + ((i + 1) >> (z + 1));
+        if (i < f - 1) s_spl[j - 1] = load_key<W>(sp, i);
         else {
 #pragma unroll
-            for (int q = 0; q < W; ++q) s_spl[j].w[q] = ~0ull;
+            for (int q = 0; q < W; ++q) s_spl[j - 1].w[q] = ~0ull;
         }
     }
     for (int j = threadIdx.x; j < f; j += kH) s_cnt[j] = 0;
     __syncthreads();
-    constexpr int kSteps = __builtin_ctz(FMAX);
     for (int64_t i0 = start; i0 < end; i0 += 4 * kH) {
         Key<W> k[4];
         int pos[4];
@@ -569,15 +581,17 @@ __global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
             }
             pos[u] = 0;
         }
-        // branch-free lower bound: pos = number of splitters below the key
+        // branch-free descent: going right at a node means the node is below the key,
+        // so the leaf reached, less FMAX, is the number of splitters below the key
 #pragma unroll
-        for (int st = kSteps - 1; st >= 0; --st) {
+        for (int u = 0; u < 4; ++u) pos[u] = 1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int nxt = pos[u] + (1 << st);
-                if (key_less<W>(s_spl[nxt - 1], k[u])) pos[u] = nxt;
-            }
+        for (int st = 0; st < kSteps; ++st) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pos[u] = 2 * pos[u] + (key_less<W>(s_spl[pos[u] - 1], k[u]) ? 1 : 0);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pos[u] -= FMAX;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t i = i0 + u * kH + threadIdx.x;
@@ -734,7 +748,7 @@ __global__ __launch_bounds__(kDThreads) void scan_apply_kernel(int64_t *x, const
 
 struct BucketArgs {
     const uint64_t *src;      // partitioned candidates (writable workspace unless single bucket)
-    uint64_t *dst;            // sorted unique run of each unit, at the unit's offset
+    uint64_t *dst;            // each unit's sorted unique keys absent from the set, at the unit's offset
     const int64_t *seg;       // [n_slots + 1] final bucket offsets
     int64_t n_slots;          // bound on the number of units
     const int32_t *ufirst;    // [n_units] first slot of each unit (consecutive buckets of one level-1 bucket)
@@ -748,7 +762,7 @@ struct BucketArgs {
     int F2;
     const uint64_t *B;        // running set (nullable)
     const int64_t *nB;        // nullable
-    int64_t *nuniq;           // [n_units] unique candidates per unit
+    int64_t *nuniq;           // [n_units] unique candidates per unit that the set does not hold
     int64_t *bstart;          // [n_units] first set element in the unit's key range
     int64_t *bcount;          // [n_units] set elements in the range
     int64_t *ucount;          // [n_units + 1] union size per unit (scanned later)
@@ -1003,39 +1017,67 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
     __syncthreads();
 }
 
-// The sorted unique run of unit s (cur[0..u) in LDS) to its place in dst, the set
-// keys of its range it shares, and the unit's counts.  A short set range is streamed
-// once and each of its keys searched among the unique keys in LDS; a long one is
-// searched per unique key instead, whichever moves fewer bytes.
+// The sorted unique run of unit s (cur[0..u) in LDS), less the keys the running set
+// already holds in the unit's range, to its place in dst, and the unit's counts:
+// the run that emit merges is then disjoint from the set keys it is merged with.
+// A short set range is streamed once and each of its keys searched among the unique
+// keys in LDS (a hit marks that key in `dup`, one bit per key, LDS the caller no
+// longer needs); a long one is searched per unique key instead, whichever moves
+// fewer bytes.
 template <int W>
 __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, const Key<W> *cur, int u, int64_t start,
-                                            int64_t bl, int64_t bh, int64_t *s_wsum) {
-    int64_t hit = 0;
+                                            int64_t bl, int64_t bh, uint32_t *dup, int64_t *s_wsum) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t nb = bh - bl;
-    const bool stream_set = nb > 0 && nb <= 56 * (int64_t)u;
-    for (int i = threadIdx.x; i < u; i += kBThreads) {
-        const Key<W> key = cur[i];
-        store_key<W>(a.dst, start + i, key);
-        if (nb > 0 && !stream_set && contains_set<W>(a.B, bl, bh, key)) ++hit;
-    }
-    if (stream_set) {
-        for (int64_t j = bl + threadIdx.x; j < bh; j += kBThreads) {
-            const Key<W> key = load_key<W>(a.B, j);
-            int lo = 0, hi = u;  // first unique key not below `key`
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (key_less<W>(cur[mid], key)) lo = mid + 1;
-                else hi = mid;
+    if (nb > 0) {
+        const bool stream_set = nb <= 56 * (int64_t)u;
+        for (int i = threadIdx.x; i < (u + 31) / 32; i += kBThreads) dup[i] = 0u;
+        __syncthreads();
+        if (stream_set) {
+            for (int64_t j = bl + threadIdx.x; j < bh; j += kBThreads) {
+                const Key<W> key = load_key<W>(a.B, j);
+                int lo = 0, hi = u;  // first unique key not below `key`
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (key_less<W>(cur[mid], key)) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < u && key_eq<W>(cur[lo], key)) atomicOr(&dup[lo >> 5], 1u << (lo & 31));
             }
-            if (lo < u && key_eq<W>(cur[lo], key)) ++hit;
+        } else {
+            for (int i = threadIdx.x; i < u; i += kBThreads)
+                if (contains_set<W>(a.B, bl, bh, cur[i])) atomicOr(&dup[i >> 5], 1u << (i & 31));
         }
+        __syncthreads();
     }
-    int64_t matches = 0;
-    if (nb > 0) block_excl_scan_i64<kBWaves>(hit, &matches, s_wsum);
+    // each wave compacts one contiguous slice of the run, in order
+    const int span = ((u + kBWaves * kWave - 1) / (kBWaves * kWave)) * kWave;
+    const int lo = w * span < u ? w * span : u, hi = lo + span < u ? lo + span : u;
+    int keep_n = 0;
+    for (int i0 = lo; i0 < hi; i0 += kWave) {
+        const int i = i0 + lane;
+        const bool keep = i < hi && (nb == 0 || !((dup[i >> 5] >> (i & 31)) & 1u));
+        keep_n += __popcll(__ballot(keep));
+    }
+    if (lane == 0) s_wsum[w] = keep_n;
+    __syncthreads();
+    int64_t base = 0, total = 0;
+#pragma unroll
+    for (int ww = 0; ww < kBWaves; ++ww) {
+        base += ww < w ? s_wsum[ww] : 0;
+        total += s_wsum[ww];
+    }
+    for (int i0 = lo; i0 < hi; i0 += kWave) {
+        const int i = i0 + lane;
+        const bool keep = i < hi && (nb == 0 || !((dup[i >> 5] >> (i & 31)) & 1u));
+        const uint64_t bal = __ballot(keep);
+        if (keep) store_key<W>(a.dst, start + base + __popcll(bal & lanemask_lt()), cur[i]);
+        base += __popcll(bal);
+    }
     if (threadIdx.x == 0) {
-        a.nuniq[s] = u;
-        a.ucount[s] = u + nb - matches;
-        a.ncount[s] = u - matches;
+        a.nuniq[s] = total;
+        a.ucount[s] = total + nb;
+        a.ncount[s] = total;
     }
 }
 
@@ -1193,7 +1235,8 @@ void bucket_kernel(BucketArgs a) {
             __syncthreads();
             cur = s_k1;
         }
-        finish_unit<W>(a, s, cur, u, start, bl, bh, s_wsum);
+        finish_unit<W>(a, s, cur, u, start, bl, bh, reinterpret_cast<uint32_t *>(cur == s_k0 ? s_k1 : s_k0),
+                       s_wsum);
         return;
     }
     if (threadIdx.x == 0) {  // an empty unit: its range holds only set keys
@@ -1341,7 +1384,7 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
             cur = nxt;
             nxt = tmp;
         }
-        finish_unit<W>(a, s, cur, u, start, bl, bh, s_wsum);
+        finish_unit<W>(a, s, cur, u, start, bl, bh, reinterpret_cast<uint32_t *>(nxt), s_wsum);
         __syncthreads();  // LDS is reused by the next unit
     }
 }
@@ -1363,7 +1406,8 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
         uint64_t *Y = a.dst + start * W;
         const int where = global_radix_sort<W>(X, X, Y, size, L.R, L.gbase, L.dtot);
         const uint64_t *res = where ? Y : X;
-        int64_t run = 0, hit = 0;
+        // first occurrences the running set does not hold, compacted in order
+        int64_t run = 0;
         for (int64_t i0 = 0; i0 < size; i0 += kDThreads) {
             const int64_t i = i0 + threadIdx.x;
             Key<W> cur;
@@ -1373,7 +1417,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
                 keep = (i == 0) || !key_eq<W>(cur, load_key<W>(res, i - 1));
             }
             __syncthreads();  // every read of this round precedes the writes (in place when res == dst)
-            if (keep && bh > bl && contains_set<W>(a.B, bl, bh, cur)) ++hit;
+            if (keep && bh > bl && contains_set<W>(a.B, bl, bh, cur)) keep = false;
             int64_t tot;
             const int64_t ex = block_excl_scan_i64(keep ? 1 : 0, &tot, L.R.wsum);
             if (keep) store_key<W>(a.dst, start + run + ex, cur);
@@ -1381,12 +1425,10 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
             __threadfence();
             __syncthreads();
         }
-        int64_t ht;
-        block_excl_scan_i64(hit, &ht, L.R.wsum);
         if (threadIdx.x == 0) {
             a.nuniq[s] = run;
-            a.ucount[s] = run + (bh - bl) - ht;
-            a.ncount[s] = run - ht;
+            a.ucount[s] = run + (bh - bl);
+            a.ncount[s] = run;
         }
         __threadfence();
         __syncthreads();
@@ -1401,7 +1443,7 @@ constexpr int kMergePer = 4;                     // merged positions per thread 
 constexpr int kEmitStep = kDThreads * kMergePer;  // outputs per staged merge window
 
 struct EmitArgs {
-    const uint64_t *runs;     // unit unique runs (at their first bucket's seg offset)
+    const uint64_t *runs;     // unit runs, disjoint from the set (at their first bucket's seg offset)
     const int64_t *seg;
     const int32_t *ufirst;
     const int64_t *n_units;
@@ -1469,14 +1511,70 @@ void emit_kernel(EmitArgs a) {
         }
         return;
     }
-    // general case: merge the run with the set keys in this slot's range, one window of
-    // kEmitStep outputs per round with both inputs staged in LDS.  Only window ends
-    // inside the merge need a split search over global memory; the four waves find
-    // those of up to kCutBatch windows at once before the windows are merged.
+    // general case.  The run holds no key of the set (the bucket kernels drop those),
+    // so the union is the merge of two disjoint sorted lists.
     constexpr int kCutBatch = 64;
-    __shared__ Key<W> sA[kEmitStep];
-    __shared__ Key<W> sB[kEmitStep + 1];  // sB[0]: the set key just before the window
-    __shared__ int64_t s_cut[kCutBatch];
+    constexpr int kRunCap = DCfg<W>::CAP;
+    constexpr size_t kWinBytes = (2 * kEmitStep + 1) * sizeof(Key<W>) + kCutBatch * 8;
+    constexpr size_t kInsBytes = kRunCap * (sizeof(Key<W>) + 4);
+    __shared__ __align__(16) char s_raw[kWinBytes > kInsBytes ? kWinBytes : kInsBytes];
+    if (nA <= kRunCap && nBs < (1ll << 31)) {
+        // The run sits in LDS.  Set key j goes to position j + r_j, r_j = run keys below
+        // it (binary search); run keys between set keys j-1 and j (indices r_{j-1} ..
+        // r_j - 1) go to i + j, i.e. below run key i lie sC[i] set keys.  Reads the run
+        // and the set range once, writes the union once.
+        Key<W> *sR = reinterpret_cast<Key<W> *>(s_raw);
+        int32_t *sC = reinterpret_cast<int32_t *>(sR + kRunCap);
+        const int nAi = (int)nA, nBi = (int)nBs, lane = threadIdx.x & (kWave - 1);
+        for (int i = threadIdx.x; i < nAi; i += kDThreads) {
+            const Key<W> k = load_key<W>(A, i);
+            sR[i] = k;
+            sC[i] = nBi;
+            if (a.novel && on + i < a.novel_cap) store_key<W>(a.novel, on + i, k);
+        }
+        __syncthreads();
+        auto below = [&](const Key<W> &key) {  // run keys below `key`
+            int lo = 0, hi = nAi;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_less<W>(sR[mid], key)) lo = mid + 1;
+                else hi = mid;
+            }
+            return lo;
+        };
+        constexpr int G = 4;
+        for (int j0 = 0; j0 < nBi; j0 += G * kDThreads) {
+            Key<W> kb[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int j = j0 + g * kDThreads + threadIdx.x;
+                if (j < nBi) kb[g] = load_key<W>(Bs, j);
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int j = j0 + g * kDThreads + threadIdx.x;  // lanes of a wave: consecutive j
+                const bool valid = j < nBi;
+                const int r = valid ? below(kb[g]) : nAi;
+                int rp = __shfl_up(r, 1);
+                if (lane == 0) rp = (valid && j > 0) ? below(load_key<W>(Bs, j - 1)) : 0;
+                if (valid) {
+                    if (ou + j + r < a.out_cap) store_key<W>(a.out, ou + j + r, kb[g]);
+                    for (int i = rp; i < r; ++i) sC[i] = j;
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nAi; i += kDThreads)
+            if (ou + i + sC[i] < a.out_cap) store_key<W>(a.out, ou + i + sC[i], sR[i]);
+        return;
+    }
+    // a run above LDS (an oversized unit): one window of kEmitStep outputs per round
+    // with both inputs staged in LDS.  Only window ends inside the merge need a split
+    // search over global memory; the four waves find those of up to kCutBatch windows
+    // at once before the windows are merged.
+    Key<W> *sA = reinterpret_cast<Key<W> *>(s_raw);          // [kEmitStep]
+    Key<W> *sB = sA + kEmitStep;                              // [kEmitStep + 1], sB[0]: the set key before the window
+    int64_t *s_cut = reinterpret_cast<int64_t *>(sB + kEmitStep + 1);  // [kCutBatch]
     const int wv = threadIdx.x / kWave;
     const int64_t n_win = ceil_div_dev(total, kEmitStep);
     int64_t i0 = 0;  // run keys consumed by earlier windows
@@ -1744,7 +1842,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             } else {
                 a.target = C::TARGET;
                 a.ovs = C::OVS2;
-                a.max_samples = C::CAP;
+                a.max_samples = C::SCAP;
                 a.fan = (int32_t *)(ws + L.fan2);
                 a.spl = (uint64_t *)(ws + L.spl2);
             }

@@ -34,6 +34,8 @@ constexpr int kRedThreads = 256;
 struct EnergyArgs {
     int n, na, nb;
     const double *h1, *eri, *vdir, *vanti, *jmat, *kmat, *jtpq, *ktpq;
+    const double *fref;             // [s][t][p] single elements on the reference determinant
+    uint64_t ref[SCI_MAX_WORDS];    // the reference: alpha 0..na-1, beta 0..nb-1
     const uint64_t *sel;
     int64_t n_sel;
     const double *psi;
@@ -90,6 +92,36 @@ __device__ double offdiag_elem(const EnergyArgs &a, const Key<W> &bra, const Key
         double v = a.h1[t * n + p];
         const double *jr = a.jtpq + (int64_t)(t * n + p) * n;  // (tp|qq) over q
         const double *kr = a.ktpq + (int64_t)(t * n + p) * n;  // (tq|qp) over q
+        // The sum over the ket's occupied spin orbitals Q may include Q = P, whose term
+        // (tp|pp) - (tp|pp) is exactly zero.  It is the reference's sum (a table entry)
+        // corrected by the spin orbitals in which the ket and the reference differ,
+        // when those are fewer than the ket's electrons.
+        Key<W> gain, loss;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            gain.w[j] = ket.w[j] & ~a.ref[j];
+            loss.w[j] = a.ref[j] & ~ket.w[j];
+        }
+        if (2 * key_popc<W>(gain) < a.na + a.nb) {
+            v = a.fref[((int64_t)sg * n + t) * n + p];
+            while (true) {
+                const int Q = lowest_bit<W>(gain);
+                if (Q < 0 || Q >= 2 * n) break;
+                clear_bit<W>(gain, Q);
+                const int s2 = Q >= n ? 1 : 0;
+                const int q = Q - s2 * n;
+                v += jr[q] - ((s2 == sg) ? kr[q] : 0.0);
+            }
+            while (true) {
+                const int Q = lowest_bit<W>(loss);
+                if (Q < 0) break;
+                clear_bit<W>(loss, Q);
+                const int s2 = Q >= n ? 1 : 0;
+                const int q = Q - s2 * n;
+                v -= jr[q] - ((s2 == sg) ? kr[q] : 0.0);
+            }
+            return (par & 1) ? -v : v;
+        }
         // occupied spin orbitals of the ket in ascending order (alpha block, then beta)
         Key<W> occ = ket;
         while (true) {
@@ -550,6 +582,10 @@ static EnergyArgs energy_args(const HamDev &d, const uint64_t *sel, int64_t n_se
     a.kmat = d.kmat;
     a.jtpq = d.jtpq;
     a.ktpq = d.ktpq;
+    a.fref = d.fref;
+    for (int j = 0; j < SCI_MAX_WORDS; ++j) a.ref[j] = 0;
+    for (int k = 0; k < d.n_alpha; ++k) a.ref[k >> 6] |= 1ull << (k & 63);
+    for (int k = d.n_orb; k < d.n_orb + d.n_beta; ++k) a.ref[k >> 6] |= 1ull << (k & 63);
     a.sel = sel;
     a.n_sel = n_sel;
     a.psi = psi;

@@ -65,6 +65,26 @@ __global__ void build_tables_kernel(const double *__restrict__ eri, double *__re
     }
 }
 
+// fref[s][t][p] = h_tp + sum over the reference's occupied spin orbitals Q of
+// (tp|qq) - [Q has spin s] (tq|qp), in the order alpha block then beta block.  The
+// reference holds alpha orbitals 0..n_alpha-1 and beta orbitals 0..n_beta-1.  For
+// any determinant D the single t <- p element is fref plus the same terms over the
+// spin orbitals D has and the reference lacks, minus those over the ones it lacks.
+__global__ void build_fref_kernel(const double *__restrict__ h1, const double *__restrict__ jtpq,
+                                  const double *__restrict__ ktpq, double *__restrict__ fref, int n, int na,
+                                  int nb) {
+    const int64_t n2 = (int64_t)n * n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * n2) return;
+    const int s = (int)(t / n2);
+    const int64_t tp = t - s * n2;  // (orbital t) * n + p
+    const double *jr = jtpq + tp * n, *kr = ktpq + tp * n;
+    double v = h1[tp];
+    for (int q = 0; q < na; ++q) v += jr[q] - (s == 0 ? kr[q] : 0.0);
+    for (int q = 0; q < nb; ++q) v += jr[q] - (s == 1 ? kr[q] : 0.0);
+    fref[t] = v;
+}
+
 // ---------------------------------------------------------------------------
 // per-launch timing
 // ---------------------------------------------------------------------------
@@ -199,9 +219,10 @@ static int32_t ham_create_impl(int32_t n_orb, int32_t n_alpha, int32_t n_beta, c
     const int64_t off_k = off_j + align(n2 * 8);
     const int64_t off_jt = off_k + align(n2 * 8);
     const int64_t off_kt = off_jt + align(n2 * n * 8);
+    const int64_t off_fref = off_kt + align(n2 * n * 8);
     const int pair_m[4] = {n_alpha, n_beta, n_orb - n_alpha, n_orb - n_beta};
     int64_t off_pairs[4];
-    int64_t cursor = off_kt + align(n2 * n * 8);
+    int64_t cursor = off_fref + align(2 * n2 * 8);
     for (int t = 0; t < 4; ++t) {
         off_pairs[t] = cursor;
         cursor += align(std::max<int64_t>(1, comb2(pair_m[t])) * 2);
@@ -246,6 +267,9 @@ static int32_t ham_create_impl(int32_t n_orb, int32_t n_alpha, int32_t n_beta, c
                        (const double *)(base + off_eri), (double *)(base + off_vdir),
                        (double *)(base + off_vanti), (double *)(base + off_j),
                        (double *)(base + off_k), (double *)(base + off_jt), (double *)(base + off_kt), (int)n);
+    SCI_LAUNCH(build_fref_kernel, dim3((unsigned)ceil_div(2 * n2, threads)), dim3(threads), 0, 0,
+               (const double *)(base + off_h1), (const double *)(base + off_jt), (const double *)(base + off_kt),
+               (double *)(base + off_fref), (int)n, n_alpha, n_beta);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
         return cleanup(fail(SCI_EHIP, "sci_ham_create: table build failed"));
 
@@ -269,6 +293,7 @@ static int32_t ham_create_impl(int32_t n_orb, int32_t n_alpha, int32_t n_beta, c
     d.kmat = (const double *)(base + off_k);
     d.jtpq = (const double *)(base + off_jt);
     d.ktpq = (const double *)(base + off_kt);
+    d.fref = (const double *)(base + off_fref);
     for (int t = 0; t < 4; ++t) d.pairs[t] = (const uint16_t *)(base + off_pairs[t]);
     h->block = block;
     *out = h;

@@ -35,6 +35,9 @@ struct HamDev {
     const double *kmat;  // [p][q] = (pq|qp)
     const double *jtpq;  // [t][p][q] = (tp|qq): the Coulomb sum of a single t <- p is a row over q
     const double *ktpq;  // [t][p][q] = (tq|qp): its exchange sum, also a row over q
+    // [s][t][p]: the single t <- p (spin s) on the reference determinant (the lowest
+    // n_alpha alpha and n_beta beta orbitals), h_tp + sum_{Q occ} [(tp|qq) - d_s (tq|qp)]
+    const double *fref;
     // lexicographic pairs (i<j) of m items as i | j<<8, for m = n_alpha,
     // n_beta, v_alpha, v_beta (index 0..3)
     const uint16_t *pairs[4];

@@ -20,6 +20,11 @@ pytestmark = pytest.mark.gpu
 
 SIGN = -(1 << 63)  # xor with this maps unsigned 64-bit order onto signed order
 SLICE = 1 << 30    # boolean selection works on at most 2^31 - 1 elements at a time
+# Two-word keys are handled as two 1-D columns (top word, low word ^ SIGN): boolean
+# row selections of 2-D tensors on this torch build return wrong rows once the result
+# exceeds 2^27 rows (measured: every regenerated key valid, 2^27 of a 2.4e8-row
+# selection not), while 1-D selections and gathers of this size are exact.
+ROWS = 1 << 28     # keys per slice of the regenerated candidates
 
 
 def _free():
@@ -35,15 +40,38 @@ def _rows_order(w1, w0):
     return w1, w0 ^ SIGN
 
 
-def _sort_unique_rows(a):
-    """Rows (hi, lo) of signed int64, sorted lexicographically and made unique."""
-    if a.shape[0] == 0:
-        return a
-    a = a[torch.sort(a[:, 1], stable=True).indices]
-    a = a[torch.sort(a[:, 0], stable=True).indices]
-    keep = torch.ones(a.shape[0], dtype=torch.bool, device=a.device)
-    keep[1:] = (a[1:] != a[:-1]).any(dim=1)
-    return a[keep]
+def _first_top_word_at_least(union, n, v):
+    """Index of the first of union[:n] whose top word is >= v (the union is sorted, so
+    its top words are non-decreasing); a host binary search over single elements,
+    which stays exact at any size."""
+    lo, hi = 0, n
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if int(union[mid, 1].item()) < v:
+            lo = mid + 1
+        else:
+            hi = mid
+    return lo
+
+
+def _sort_unique_cols(h, l):
+    """Pairs (h[i], l[i]) of signed int64 columns, sorted lexicographically and made
+    unique; returns the two columns."""
+    if h.shape[0] == 0:
+        return h, l
+    idx = torch.sort(l, stable=True).indices
+    h, l = h[idx], l[idx]
+    idx = torch.sort(h, stable=True).indices
+    h, l = h[idx], l[idx]
+    del idx
+    keep = torch.ones(h.shape[0], dtype=torch.bool, device=h.device)
+    keep[1:] = (h[1:] != h[:-1]) | (l[1:] != l[:-1])
+    return h[keep], l[keep]
+
+
+def _merge_cols(acc, h, l):
+    """acc (two columns, sorted unique) merged with the pairs (h, l)."""
+    return _sort_unique_cols(torch.cat([acc[0], h]), torch.cat([acc[1], l]))
 
 
 def test_medium_full_generation_and_dedup():
@@ -149,52 +177,51 @@ def test_large_streamed_minibatch_exact_ranges():
     # contiguous slice.  Per group of ranges, every candidate of the mini-batch is
     # regenerated chunk by chunk and those of the group's ranges are kept; each range
     # is then sorted and made unique by the library sort and compared with its slice.
-    hi = union[:n, 1].contiguous()
     R = 16
-    hb = torch.unique(hi[torch.tensor([(r * n) // R for r in range(1, R)], device="cuda")], sorted=True)
-    n_ranges = hb.shape[0] + 1
-    starts = torch.searchsorted(hi, hb).tolist()
+    cuts = sorted(set(int(union[(r * n) // R, 1].item()) for r in range(1, R)))
+    hb = torch.tensor(cuts, dtype=torch.int64, device="cuda")
+    n_ranges = len(cuts) + 1
+    starts = [_first_top_word_at_least(union, n, v) for v in cuts]
     slices = list(zip([0] + starts, starts + [n]))
-    del hi
-    _free()
     sel_ids = torch.searchsorted(hb, sel[:, 1].contiguous(), right=True)
     G = 4
     checked = 0
     for g0 in range(0, n_ranges, G):
         group = list(range(g0, min(g0 + G, n_ranges)))
-        parts = {r: [] for r in group}
+        # each range's distinct keys so far (its selected keys to start with), merged
+        # with every chunk's candidates in the range as the chunks are regenerated:
+        # memory stays near the range's share of the union
+        acc = {}
+        s1, s0 = _rows_order(sel[:, 1].contiguous(), sel[:, 0].contiguous())
+        for r in group:
+            m = sel_ids == r
+            acc[r] = _sort_unique_cols(s1[m], s0[m])
+        seen = {r: 0 for r in group}
         for a in range(0, total, chunk):
             b = min(a + chunk, total)
             k, _, _, n_k, fl = sci.gen_coupled(h, dets, exc_begin=a, exc_end=b)
             torch.cuda.synchronize()
             assert sci.check_flags(fl, "gen") == 0 and int(n_k.item()) == b - a
-            for c in range(0, b - a, SLICE):
-                kc = k[c:c + SLICE]
-                ids = torch.searchsorted(hb, kc[:, 1].contiguous(), right=True)
+            for c in range(0, b - a, ROWS):
+                k1, k0 = _rows_order(k[c:c + ROWS, 1].contiguous(), k[c:c + ROWS, 0].contiguous())
+                ids = torch.searchsorted(hb, k1, right=True)
                 for r in group:
-                    # unique per chunk already: a range's candidates over all chunks can
-                    # exceed one sort's 2^31 - 1 elements, their distinct keys cannot
-                    sel_r = kc[ids == r]
-                    w1, w0 = _rows_order(sel_r[:, 1], sel_r[:, 0])
-                    parts[r].append(_sort_unique_rows(torch.stack([w1, w0], dim=1)))
-                    del sel_r, w1, w0
-                del ids
+                    m = ids == r
+                    p1, p0 = k1[m], k0[m]
+                    seen[r] += p1.shape[0]
+                    acc[r] = _merge_cols(acc[r], p1, p0)
+                    del m, p1, p0
+                del ids, k1, k0
             del k
             _free()
         for r in group:
-            s_r = sel[sel_ids == r]
-            w1, w0 = _rows_order(s_r[:, 1], s_r[:, 0])
-            parts[r].append(torch.stack([w1, w0], dim=1))
-            cand = torch.cat(parts.pop(r))
-            got_n = cand.shape[0]
-            expect = _sort_unique_rows(cand)
-            del cand, w1, w0, s_r
+            e1, e0 = acc.pop(r)
             i, j = slices[r]
             u1, u0 = _rows_order(union[i:j, 1], union[i:j, 0])
-            assert torch.equal(expect, torch.stack([u1, u0], dim=1)), f"union differs in range {r} [{i}, {j})"
-            checked += expect.shape[0]
-            say(f"  range {r} [{i}, {j}): {j - i} keys exact from {got_n} per-chunk distinct candidates")
-            del expect, u1, u0
+            assert torch.equal(e1, u1) and torch.equal(e0, u0), f"union differs in range {r} [{i}, {j})"
+            checked += e1.shape[0]
+            say(f"  range {r} [{i}, {j}): {j - i} keys exact from {seen[r]} candidates")
+            del e1, e0, u1, u0
             _free()
     assert checked == n, f"ranges hold {checked} unique keys, the union {n}"
     say(f"  all {n} union keys checked exactly in {n_ranges} ranges")
@@ -212,16 +239,27 @@ def test_large_streamed_minibatch_exact_ranges():
     torch.cuda.synchronize()
     assert sci.check_flags(fl, "index") == 0
     assert bool((idx >= 0).all()), "a generated candidate is missing from the index"
-    for c in range(0, chunk, SLICE // 4):
-        assert torch.equal(union[idx[c:c + SLICE // 4]], k[c:c + SLICE // 4])
+    # gathers read from union slices of 2^28 keys (a gather from the whole set buffer,
+    # 6.6e9 elements, is refused by this torch build's index kernel)
+    for c in range(0, chunk, 1 << 26):
+        ic = idx[c:c + (1 << 26)]
+        k1, k0 = k[c:c + (1 << 26), 1].contiguous(), k[c:c + (1 << 26), 0].contiguous()
+        for u0 in range(0, n, 1 << 28):
+            u1 = min(u0 + (1 << 28), n)
+            m = (ic >= u0) & (ic < u1)
+            part = union[u0:u1]
+            j = ic[m] - u0
+            assert torch.equal(part[:, 1][j], k1[m]) and torch.equal(part[:, 0][j], k0[m])
+            del m, part, j
+        del ic, k1, k0
     del k, idx
     _free()
     # against the oracle on one range's slice of the union: members at random positions
     # and the same keys with their lowest bit flipped (same top word, so same range)
     i, j = slices[n_ranges // 2]
     rng = np.random.Generator(np.random.PCG64(2604157690))
-    pos = torch.from_numpy(rng.integers(i, j, size=500_000)).cuda()
-    members = union[pos]
+    pos = torch.from_numpy(rng.integers(0, j - i, size=500_000)).cuda()
+    members = union[i:j][pos]
     flipped = members.clone()
     flipped[:, 0] ^= 1
     cand = torch.cat([members, flipped])
@@ -249,7 +287,7 @@ def _strictly_ascending_rows(union, n):
 def test_large_whole_selected_space_streamed():
     """All 200,000 sources of the large workload (7.2e10 candidates) streamed in pool
     chunks of 2^29 into one set on one GPU.  Checked at full size: no overflow, strictly
-    ascending, S contained; and exactly on two sampled key ranges (cut at top-word
+    ascending; and exactly on two sampled key ranges (cut at top-word
     values of union keys) against a library sort + unique of every candidate of the
     whole stream that falls in them, regenerated chunk by chunk."""
     sci = require_gpu()
@@ -269,28 +307,31 @@ def test_large_whole_selected_space_streamed():
     assert s.dets.shape[0] <= n <= cap
     _free()
     assert _strictly_ascending_rows(union, n), "union not strictly ascending"
-    # S is contained: each selected key sits at its searchsorted position
-    hi = union[:n, 1].contiguous()
     # two sampled ranges of about 4e7 union keys, cut at top-word values
     ranges = []
     for f in (0.3, 0.7):
         i0 = int(f * n)
-        lo_v = hi[i0]
-        hi_v = hi[min(i0 + 40_000_000, n - 1)]
-        if int(hi_v.item()) == int(lo_v.item()):
+        lo_v = int(union[i0, 1].item())
+        hi_v = int(union[min(i0 + 40_000_000, n - 1), 1].item())
+        if hi_v == lo_v:
             hi_v = lo_v + 1
-        i = int(torch.searchsorted(hi, lo_v.reshape(1)).item())
-        j = int(torch.searchsorted(hi, hi_v.reshape(1)).item())
-        ranges.append((int(lo_v.item()), int(hi_v.item()), i, j))
-    del hi
-    _free()
-    parts = [[] for _ in ranges]
+        ranges.append((lo_v, hi_v, _first_top_word_at_least(union, n, lo_v), _first_top_word_at_least(union, n, hi_v)))
+    # each range's distinct keys, merged with every chunk's candidates in it as the
+    # chunks are regenerated
+    empty = sel.new_empty(0)
+    acc = [(empty, empty) for _ in ranges]
+    seen = [0 for _ in ranges]
 
-    def take(k):
-        w1 = k[:, 1]
-        for (lo, hi_, _, _), p in zip(ranges, parts):
-            m = (w1 >= lo) & (w1 < hi_)
-            p.append(k[m])
+    def take(k_all):
+        for c in range(0, k_all.shape[0], ROWS):
+            k1, k0 = _rows_order(k_all[c:c + ROWS, 1].contiguous(), k_all[c:c + ROWS, 0].contiguous())
+            for q, (lo, hi_, _, _) in enumerate(ranges):
+                m = (k1 >= lo) & (k1 < hi_)
+                p1, p0 = k1[m], k0[m]
+                seen[q] += p1.shape[0]
+                acc[q] = _merge_cols(acc[q], p1, p0)
+                del m, p1, p0
+            del k1, k0
 
     for a in range(0, total, chunk):
         b = min(a + chunk, total)
@@ -301,15 +342,12 @@ def test_large_whole_selected_space_streamed():
     torch.cuda.synchronize()
     assert sci.check_flags(fl, "gen") == 0
     take(sel)
-    for (lo, hi_, i, j), p in zip(ranges, parts):
-        cand = torch.cat(p)
-        w1, w0 = _rows_order(cand[:, 1], cand[:, 0])
-        expect = _sort_unique_rows(torch.stack([w1, w0], dim=1))
-        del cand, w1, w0
+    for q, (lo, hi_, i, j) in enumerate(ranges):
+        e1, e0 = acc[q]
         u1, u0 = _rows_order(union[i:j, 1], union[i:j, 0])
-        assert torch.equal(expect, torch.stack([u1, u0], dim=1)), f"union differs in [{i}, {j})"
-        say(f"  range [{i}, {j}): {j - i} keys exact from {sum(x.shape[0] for x in p)} candidates")
-        del expect, u1, u0
+        assert torch.equal(e1, u1) and torch.equal(e0, u0), f"union differs in [{i}, {j})"
+        say(f"  range [{i}, {j}): {j - i} keys exact from {seen[q]} candidates")
+        del e1, e0, u1, u0
         _free()
-    del parts, union
+    del acc, union
     _free()
