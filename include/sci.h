@@ -283,6 +283,27 @@ int32_t sci_energy_batch_destroy(sci_energy_batch_t batch);
 int32_t sci_energy_batched(sci_energy_batch_t batch, sci_stream_t stream);
 
 /*
+ * sci_energy for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and results as sci_energy (method SCI_ENERGY_AUTO, bit-identical
+ * output) without the workspace: the library keeps its own scratch, one
+ * file-scope device array per GPU of sci_energy_workspace_bytes(
+ * sci_energy_noalloc_max_sel()) bytes (about 19 MB), held until the process
+ * ends.  Calls no hipMalloc/hipFree; the first call on a device looks up that
+ * device's scratch address (hipGetSymbolAddress) and keeps it.
+ *
+ * n_sel at most sci_energy_noalloc_max_sel() (2^18 = 262,144), else
+ * SCI_ECAPACITY before anything is enqueued.  Every call on one GPU shares that
+ * GPU's scratch, so calls whose work overlaps on one GPU (different streams,
+ * or host threads without ordering) race and give undefined results; calls
+ * ordered on one stream are safe.  Errors: as sci_energy, plus SCI_ECAPACITY.
+ */
+int64_t sci_energy_noalloc_max_sel(void);
+int32_t sci_energy_noalloc(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                           double *energy, double *h_psi, double *grad,
+                           uint32_t *dev_flags, sci_stream_t stream);
+
+/*
  * Streaming generation + de-duplication through a device pool (paper
  * section 4.3: mini-batches of bounded size, reduced as they are produced;
  * section 4.1: every batch is merged into the running unique set).

@@ -63,6 +63,10 @@ _lib.sci_energy_ex.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _i32, _P, _sz, _P, 
 _lib.sci_energy_ex.restype = _i32
 _lib.sci_energy_method.argtypes = [_P, _i64]
 _lib.sci_energy_method.restype = _i32
+_lib.sci_energy_noalloc_max_sel.argtypes = []
+_lib.sci_energy_noalloc_max_sel.restype = _i64
+_lib.sci_energy_noalloc.argtypes = [_P, _P, _i64, _P, _P, _P, _P, _P, _P]
+_lib.sci_energy_noalloc.restype = _i32
 _lib.sci_stream_workspace_bytes.argtypes = [_P, _i64]
 _lib.sci_stream_workspace_bytes.restype = _sz
 _lib.sci_stream_dedup.argtypes = [_P, _P, _i64, _i64, _i64, _i64, _P, _P, _P, _P, _i64, _P,
@@ -298,6 +302,23 @@ def sci_energy(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, workspace, worksp
     _check(_lib.sci_energy_ex(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
                               int(method), _ptr(workspace), workspace_bytes, _ptr(dev_flags), _stream(stream)),
            "sci_energy")
+
+
+def sci_energy_noalloc_max_sel() -> int:
+    return int(_lib.sci_energy_noalloc_max_sel())
+
+
+def sci_energy_noalloc(ham: Ham, sel, n_sel, psi, energy, h_psi, grad, dev_flags, stream=None):
+    """sci_energy without a workspace: the library's own per-device scratch (n_sel limited)."""
+    dev = sel.device
+    _check_keys(sel, ham.W, n_sel, "sel")
+    _check_vec(psi, torch.float64, n_sel, "psi", dev)
+    _check_vec(energy, torch.float64, 1, "energy", dev)
+    _check_vec(h_psi, torch.float64, n_sel, "h_psi", dev)
+    _check_vec(grad, torch.float64, n_sel, "grad", dev)
+    _check_vec(dev_flags, torch.int32, 1, "dev_flags", dev)
+    _check(_lib.sci_energy_noalloc(ham.handle, _ptr(sel), n_sel, _ptr(psi), _ptr(energy), _ptr(h_psi), _ptr(grad),
+                                   _ptr(dev_flags), _stream(stream)), "sci_energy_noalloc")
 
 
 def sci_stream_workspace_bytes(ham: Ham, chunk: int) -> int:

@@ -707,6 +707,63 @@ extern "C" int32_t sci_energy(sci_ham_t ham, const uint64_t *sel, int64_t n_sel,
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free variant: the workspace lives in a file-scope device array
+// ---------------------------------------------------------------------------
+
+namespace sci {
+
+constexpr int64_t kNoAllocMaxSel = 1 << 18;
+constexpr size_t kNoAllocBytes = energy_ws(kNoAllocMaxSel);
+
+// One copy per device, held until the process ends.  In host code `scratch` names
+// a host-side stand-in, never the device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch, looked up on the first call per device.
+static int32_t scratch_address(char **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(SCI_EHIP, "sci_energy_noalloc: no usable current device (%d)", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SCI_EHIP, "sci_energy_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SCI_OK;
+}
+
+}  // namespace sci
+
+extern "C" int64_t sci_energy_noalloc_max_sel(void) { return kNoAllocMaxSel; }
+
+extern "C" int32_t sci_energy_noalloc(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, const double *psi,
+                                      double *energy, double *h_psi, double *grad, uint32_t *dev_flags,
+                                      sci_stream_t stream) {
+    set_error("");
+    int32_t rc = energy_check("sci_energy_noalloc", ham, sel, n_sel, psi, energy, dev_flags);
+    if (rc != SCI_OK) return rc;
+    if (n_sel > kNoAllocMaxSel)
+        return fail(SCI_ECAPACITY, "sci_energy_noalloc: n_sel=%lld exceeds the scratch limit of %lld determinants",
+                    (long long)n_sel, (long long)kNoAllocMaxSel);
+    char *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != SCI_OK) return rc;
+    // every scratch word the kernels read is written earlier in the same call, so
+    // nothing needs clearing; launches bypass the per-launch profiler (it creates events)
+    const EnergyArgs a = energy_args(ham->dev, sel, n_sel, psi, energy, h_psi, grad, ws, dev_flags);
+    return energy_launch(ham->dev.W, a, (hipStream_t)stream, false, pick_method(ham->dev, n_sel, SCI_ENERGY_AUTO));
+}
+
+// ---------------------------------------------------------------------------
 // batches of systems: the same per-block work as sci_energy, over tile lists
 // that cover every system, so each system's results are bit-identical to its
 // own sci_energy call
