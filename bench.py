@@ -70,6 +70,9 @@ def parse():
                     help="pool chunk in candidates (0: time 2^28, 2^29, 2^30 once each and keep the fastest)")
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_OUTPUT"),
+                    help="print a markdown table of the kernels of the timed steps of a profiled run of this "
+                         "script (rocprofv3 --kernel-trace CSV + that run's JSON line), then exit")
     ap.add_argument("--record-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "WORKLOAD"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
                          "profiles/kernel_traffic.json entries for WORKLOAD, then exit")
@@ -204,6 +207,50 @@ def record_traffic(fetch_dir, write_dir, workload):
                                   "calibration": f"{round(gib)} GiB device copy", "kernels": kernels}
     json.dump(rec, open(path, "w"), indent=1)
     print(f"{len(kernels)} kernels recorded for {workload} (read x{read_scale:.3f}, write x{write_scale:.3f})")
+
+
+def summarize_trace(trace_csv, bench_out):
+    """Per-kernel durations of the timed steps of a profiled run: for every kernel the
+    bench saw, its last steps x launches_per_step dispatches in the trace (dispatch
+    order), next to the average the bench measured with HIP events in the same run."""
+    import csv
+    res = None
+    for line in open(bench_out):
+        line = line.strip()
+        if line.startswith("{") and '"metric"' in line:
+            res = json.loads(line)
+    if res is None:
+        raise SystemExit(f"no JSON line in {bench_out}")
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r.get("Dispatch_Id") or 0))
+    by = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        by.setdefault(name, []).append(ns)
+    steps = res["steps"]
+    m = re.search(r"W=(\d)", res["config"]["workload"])
+    W = m.group(1) if m else "1"
+    out = []
+    for bench_name, k in res["kernels"].items():
+        n_last = int(round(k["launches_per_step"] * steps))
+        fam = family(bench_name)
+        want = [W if a == "W" else FANOUT.get(a, a) for a in _template_args(bench_name, fam)]
+        for t, d_all in by.items():
+            tn = t.split("(")[0].replace("void ", "") if "<" not in t.split("(")[0] else t
+            if family(tn.split("(")[0].split("<")[0] + ("<" if "<" in t else "")) != fam and \
+                    t.split("(")[0].replace("void ", "").split("::")[-1].split("<")[0] != fam:
+                continue
+            if _template_args(t, fam) != want:
+                continue
+            d = d_all[-n_last:] if n_last else []
+            if d:
+                out.append((t, len(d), sum(d) / len(d) / 1e6, k["ms_per_launch"], k["launches_per_step"]))
+    out.sort(key=lambda x: -x[2] * x[4])
+    print("| kernel | dispatches (timed steps) | avg ms (trace) | avg ms (bench events) | ms per step (trace) |")
+    print("|---|---:|---:|---:|---:|")
+    for t, n, ms, bms, lps in out:
+        print(f"| `{t.split('(')[0].replace('void ', '')}` | {n} | {ms:.3f} | {bms:.3f} | {ms * lps:.1f} |")
 
 
 def copy_bandwidth(torch, dev, gib=4.0, reps=3):
@@ -660,7 +707,9 @@ def whole_extras(args, torch, sci, ham, sel):
     ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     free_bytes = torch.cuda.mem_get_info(dev)[0]
-    cap = int(min(total + n_sel, (free_bytes - (4 << 30)) // (2 * W * 8)))
+    # the union lies in the determinants of excitation level <= 4 of the reference
+    # (5.55e9 for this system), so larger set buffers would stay unused
+    cap = int(min(total + n_sel, 5_600_000_000, (free_bytes - (16 << 30)) // (2 * W * 8)))
     set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
     set_b = torch.empty_like(set_a)
     n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
@@ -678,7 +727,10 @@ def whole_extras(args, torch, sci, ham, sel):
     t_ms = _median_ms(run, 1, torch)
     sci.check_flags(flags, "whole selected space")
     n_union = int(n_out.item())
+    peak = torch.cuda.max_memory_allocated(dev)
     res = set_b if fb[0] else set_a
+    del ws, set_a, set_b
+    torch.cuda.empty_cache()
     # strictly ascending at full size, checked on the device in slices
     ok = True
     for a0 in range(0, n_union - 1, 1 << 30):
@@ -693,8 +745,8 @@ def whole_extras(args, torch, sci, ham, sel):
            "candidates_per_s": total / (t_ms / 1000.0), "n_unique_union": n_union, "union_ascending": ok,
            "redundancy": total / n_union, "set_capacity": cap,
            "device_bytes": {"pool_and_workspace": ws_bytes, "set_buffers": 2 * cap * W * 8,
-                            "peak_allocated": torch.cuda.max_memory_allocated(dev)}}
-    del ws, set_a, set_b, res
+                            "peak_allocated": peak}}
+    del res
     torch.cuda.empty_cache()
     return out
 
@@ -882,6 +934,9 @@ def main():
     args = parse()
     if args.record_traffic:
         record_traffic(*args.record_traffic)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build", file=sys.stderr)

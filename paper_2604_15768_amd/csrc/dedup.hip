@@ -1034,15 +1034,28 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
         for (int i = threadIdx.x; i < (u + 31) / 32; i += kBThreads) dup[i] = 0u;
         __syncthreads();
         if (stream_set) {
-            for (int64_t j = bl + threadIdx.x; j < bh; j += kBThreads) {
-                const Key<W> key = load_key<W>(a.B, j);
-                int lo = 0, hi = u;  // first unique key not below `key`
+            // each thread takes G consecutive set keys: one search for the first, then
+            // the position advances along the run (it never decreases)
+            constexpr int G = 8;
+            for (int64_t jt = bl; jt < bh; jt += (int64_t)G * kBThreads) {
+                const int64_t jb = jt + (int64_t)threadIdx.x * G;
+                if (jb >= bh) continue;
+                Key<W> kb[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (jb + g < bh) kb[g] = load_key<W>(a.B, jb + g);
+                int lo = 0, hi = u;  // first unique key not below kb[0]
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (key_less<W>(cur[mid], key)) lo = mid + 1;
+                    if (key_less<W>(cur[mid], kb[0])) lo = mid + 1;
                     else hi = mid;
                 }
-                if (lo < u && key_eq<W>(cur[lo], key)) atomicOr(&dup[lo >> 5], 1u << (lo & 31));
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if (jb + g >= bh) break;
+                    if (g) while (lo < u && key_less<W>(cur[lo], kb[g])) ++lo;
+                    if (lo < u && key_eq<W>(cur[lo], kb[g])) atomicOr(&dup[lo >> 5], 1u << (lo & 31));
+                }
             }
         } else {
             for (int i = threadIdx.x; i < u; i += kBThreads)
@@ -1478,7 +1491,7 @@ __device__ int64_t wave_merge_path(const uint64_t *A, int64_t nA, const uint64_t
 }
 
 template <int W>
-__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(W == 1 ? 6 : 4, 8)))
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
     const int64_t s = blockIdx.x;  // unit
@@ -1542,25 +1555,34 @@ void emit_kernel(EmitArgs a) {
             }
             return lo;
         };
-        constexpr int G = 4;
-        for (int j0 = 0; j0 < nBi; j0 += G * kDThreads) {
+        // each thread takes G consecutive set keys: one search for the first, then the
+        // count advances along the run (r_j never decreases with j)
+        constexpr int G = 8;
+        for (int jt = 0; jt < nBi; jt += G * kDThreads) {
+            const int jb = jt + (int)threadIdx.x * G;
             Key<W> kb[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int j = j0 + g * kDThreads + threadIdx.x;
-                if (j < nBi) kb[g] = load_key<W>(Bs, j);
+            for (int g = 0; g < G; ++g)
+                if (jb + g < nBi) kb[g] = load_key<W>(Bs, jb + g);
+            int r[G];
+            r[0] = jb < nBi ? below(kb[0]) : nAi;
+#pragma unroll
+            for (int g = 1; g < G; ++g) {
+                int x = r[g - 1];
+                if (jb + g < nBi)
+                    while (x < nAi && key_less<W>(sR[x], kb[g])) ++x;
+                r[g] = x;
             }
+            // run keys below the set key just before this thread's first one: the previous
+            // lane's last count, searched afresh by the first lane of a wave
+            int rp = __shfl_up(r[G - 1], 1);
+            if (lane == 0) rp = (jb < nBi && jb > 0) ? below(load_key<W>(Bs, jb - 1)) : 0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int j = j0 + g * kDThreads + threadIdx.x;  // lanes of a wave: consecutive j
-                const bool valid = j < nBi;
-                const int r = valid ? below(kb[g]) : nAi;
-                int rp = __shfl_up(r, 1);
-                if (lane == 0) rp = (valid && j > 0) ? below(load_key<W>(Bs, j - 1)) : 0;
-                if (valid) {
-                    if (ou + j + r < a.out_cap) store_key<W>(a.out, ou + j + r, kb[g]);
-                    for (int i = rp; i < r; ++i) sC[i] = j;
-                }
+                const int j = jb + g;
+                if (j >= nBi) break;
+                if (ou + j + r[g] < a.out_cap) store_key<W>(a.out, ou + j + r[g], kb[g]);
+                for (int i = (g ? r[g - 1] : rp); i < r[g]; ++i) sC[i] = j;
             }
         }
         __syncthreads();
