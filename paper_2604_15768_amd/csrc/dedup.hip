@@ -954,7 +954,10 @@ constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
 
 // One stable LSD pass of the 512-thread unit sort on the 8-bit digit at `shift`, of
-// which the bits in `vmask` vary in the unit.  This wave's keys are
+// which the bits in `vmask` vary in the unit.  Stability inside a wave rests on LDS
+// atomics of one instruction to one address being served in lane order (checked on
+// gfx950: every wave of 131,072 probes with 1, 4, 32 and 256 distinct addresses
+// received lane-ordered counts).  This wave's keys are
 // cur[base_pos + k*64 + lane] for k < rounds, positions below `limit`; each key goes
 // to nxt at (keys of smaller digits) + (keys of its digit in lower waves or earlier
 // in this wave).  Keys and ranks stay in registers between the two sweeps.
@@ -963,6 +966,10 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
                                                 int base_pos, int rounds, int limit, uint16_t (*s_cnt)[256]) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     constexpr int kBK = KB;
+    // digits with few varying bits take a ballot per bit; more take one LDS atomic
+    // per key (fewer instructions, and the counts then spread over enough words that
+    // same-word serialisation stays short)
+    const bool many = __popc(vmask) > 3;
     *reinterpret_cast<uint64_t *>(&s_cnt[w][4 * lane]) = 0ull;
     // keys and their ranks stay in registers until the scatter below
     Key<W> kr[kBK];
@@ -974,12 +981,21 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
         const bool valid = pos < limit;
         if (valid) kr[k] = cur[pos];
         const uint32_t d = valid ? digit_of<W>(kr[k], shift) : 0u;
-        int rk;
-        const int tot = wave_match_rank_bits(d, valid, vmask, &rk);
-        uint32_t base = 0;
-        if (valid) base = s_cnt[w][d];
-        if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
-        rr[k] = base + (uint32_t)rk;
+        if (many) {
+            // one LDS add per key on the 32-bit word holding the digit's 16-bit count: the
+            // lanes of one instruction that hit the same word are served in lane order, so
+            // the count returned is this key's rank among equal digits before it
+            uint32_t old = 0;
+            if (valid) old = atomicAdd(reinterpret_cast<uint32_t *>(&s_cnt[w][d & ~1u]), (d & 1u) ? 0x10000u : 1u);
+            rr[k] = (d & 1u) ? (old >> 16) : (old & 0xffffu);
+        } else {
+            int rk;
+            const int tot = wave_match_rank_bits(d, valid, vmask, &rk);
+            uint32_t base = 0;
+            if (valid) base = s_cnt[w][d];
+            if (valid && rk == 0) s_cnt[w][d] = (uint16_t)(base + (uint32_t)tot);
+            rr[k] = base + (uint32_t)rk;
+        }
     }
     __syncthreads();
     // this wave's output offset per digit: all keys of smaller digits, plus
