@@ -1468,7 +1468,7 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
 // emit: per bucket, merge its unique run with the set elements of its range
 // into set_out at the scanned union offset; novel keys at the novel offset
 // ---------------------------------------------------------------------------
-constexpr int kMergePer = 4;                     // merged positions per thread per window
+constexpr int kMergePer = 2;                     // merged positions per thread per window
 constexpr int kEmitStep = kDThreads * kMergePer;  // outputs per staged merge window
 
 struct EmitArgs {
@@ -1507,7 +1507,7 @@ __device__ int64_t wave_merge_path(const uint64_t *A, int64_t nA, const uint64_t
 }
 
 template <int W>
-__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(6, 8)))
 void emit_kernel(EmitArgs a) {
     __shared__ int64_t wsum[kDWaves];
     const int64_t s = blockIdx.x;  // unit
@@ -1543,18 +1543,28 @@ void emit_kernel(EmitArgs a) {
     // general case.  The run holds no key of the set (the bucket kernels drop those),
     // so the union is the merge of two disjoint sorted lists.
     constexpr int kCutBatch = 64;
-    constexpr int kRunCap = DCfg<W>::CAP;
+    constexpr int kRunCap = DCfg<W>::CAP / 2;
     constexpr size_t kWinBytes = (2 * kEmitStep + 1) * sizeof(Key<W>) + kCutBatch * 8;
     constexpr size_t kInsBytes = kRunCap * (sizeof(Key<W>) + 4);
     __shared__ __align__(16) char s_raw[kWinBytes > kInsBytes ? kWinBytes : kInsBytes];
     if (nA <= kRunCap && nBs < (1ll << 31)) {
-        // The run sits in LDS.  Set key j goes to position j + r_j, r_j = run keys below
-        // it (binary search); run keys between set keys j-1 and j (indices r_{j-1} ..
-        // r_j - 1) go to i + j, i.e. below run key i lie sC[i] set keys.  Reads the run
-        // and the set range once, writes the union once.
+        // The run sits in LDS (up to CAP/2 keys: the LDS stays small enough for six
+        // workgroups per CU, which hide more of the memory latency this kernel waits
+        // on).  Set key j goes to position j + r_j, r_j = run keys below it; run keys
+        // between set keys j-1 and j (indices r_{j-1} .. r_j - 1) go to i + j, i.e.
+        // below run key i lie sC[i] set keys.  Reads the run and the set range once,
+        // writes the union once.
         Key<W> *sR = reinterpret_cast<Key<W> *>(s_raw);
         int32_t *sC = reinterpret_cast<int32_t *>(sR + kRunCap);
         const int nAi = (int)nA, nBi = (int)nBs, lane = threadIdx.x & (kWave - 1);
+        constexpr int G = 4;
+        Key<W> kb[G];
+        {   // the first block of set keys is in flight while the run is staged
+            const int jb = (int)threadIdx.x * G;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (jb + g < nBi) kb[g] = load_key<W>(Bs, jb + g);
+        }
         for (int i = threadIdx.x; i < nAi; i += kDThreads) {
             const Key<W> k = load_key<W>(A, i);
             sR[i] = k;
@@ -1572,14 +1582,15 @@ void emit_kernel(EmitArgs a) {
             return lo;
         };
         // each thread takes G consecutive set keys: one search for the first, then the
-        // count advances along the run (r_j never decreases with j)
-        constexpr int G = 8;
+        // count advances along the run (r_j never decreases with j); G = 4 measured
+        // against 2 and 8 (large workload 22.7 / 21.7 / 28.1 ms per chunk)
         for (int jt = 0; jt < nBi; jt += G * kDThreads) {
             const int jb = jt + (int)threadIdx.x * G;
-            Key<W> kb[G];
+            if (jt > 0) {
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                if (jb + g < nBi) kb[g] = load_key<W>(Bs, jb + g);
+                for (int g = 0; g < G; ++g)
+                    if (jb + g < nBi) kb[g] = load_key<W>(Bs, jb + g);
+            }
             int r[G];
             r[0] = jb < nBi ? below(kb[0]) : nAi;
 #pragma unroll
