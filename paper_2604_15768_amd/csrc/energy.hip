@@ -192,14 +192,15 @@ __device__ double diag_elem(const EnergyArgs &a, const Key<W> &d) {
 // Connected pairs found by a wave wait in a per-wave LDS queue, in ascending
 // column order, and are evaluated 64 at a time with every lane busy (one
 // entry per lane, the row's determinant fetched from its owner lane); each row
-// lane then adds its own entries in queue order, so every row still sums its
-// terms in ascending j.
+// lane then adds its own entries in queue order (their positions, recorded as
+// they were queued), so every row still sums its terms in ascending j.
 constexpr int kQueue = 2 * kWave;
+constexpr int kSlots = 8;  // queued entries per row lane before the queue is flushed
 
 template <int W>
 __device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &di, int n_q, const uint32_t *q_ent,
-                                           double *q_val, const Key<W> *tile_keys, const double *tile_psi,
-                                           double &acc) {
+                                           double *q_val, const uint8_t *q_pos, int mine, const Key<W> *tile_keys,
+                                           const double *tile_psi, double &acc) {
     const int lane = threadIdx.x & (kWave - 1);
     for (int base = 0; base < n_q; base += kWave) {
         const int k = base + lane;
@@ -219,8 +220,7 @@ __device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &d
         }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int k = 0; k < n_q; ++k)
-        if ((int)(q_ent[k] >> 16) == lane) acc += q_val[k];
+    for (int j = 0; j < mine; ++j) acc += q_val[q_pos[lane * kSlots + j]];
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -230,6 +230,7 @@ struct HpsiLds {
     double tile_psi[kColTile];
     uint32_t ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | (four moved << 15) | column
     double val[kRowThreads / kWave][kQueue];
+    uint8_t pos[kRowThreads / kWave][kWave * kSlots];  // queue positions of each row lane's entries
 };
 
 // rows [rb*256, rb*256+256) against column block cb of n_col
@@ -257,6 +258,7 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
     }
     uint32_t *q_ent = S.ent[w];
     double *q_val = S.val[w];
+    uint8_t *q_pos = S.pos[w];
     const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)n_col), (int64_t)kColTile) * kColTile;
     const int64_t c0 = (int64_t)cb * per;
     const int64_t c1 = min<int64_t>(c0 + per, a.n_sel);
@@ -285,7 +287,8 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
             }
         }
         __syncthreads();
-        int n_q = 0;  // wave-uniform
+        int n_q = 0;   // wave-uniform
+        int mine = 0;  // this row lane's queued entries
         for (int t = 0; t < cnt; ++t) {
             const Key<W> dj = tile_keys[t];
             Key<W> x;
@@ -295,19 +298,23 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
             const bool conn = active && (pc == 2 || pc == 4);
             const uint64_t bal = __ballot(conn);
             if (bal == 0ull) continue;
-            if (conn)
-                q_ent[n_q + __popcll(bal & lanemask_lt())] =
-                    ((uint32_t)lane << 16) | ((uint32_t)(pc == 4) << 15) | (uint32_t)t;
+            if (conn) {
+                const int p = n_q + __popcll(bal & lanemask_lt());
+                q_ent[p] = ((uint32_t)lane << 16) | ((uint32_t)(pc == 4) << 15) | (uint32_t)t;
+                q_pos[lane * kSlots + mine] = (uint8_t)p;
+                ++mine;
+            }
             n_q += __popcll(bal);
-            if (n_q >= kWave) {
+            if (n_q >= kWave || __ballot(mine >= kSlots) != 0ull) {
                 __builtin_amdgcn_wave_barrier();
-                flush_queue<W>(a, di, n_q, q_ent, q_val, tile_keys, tile_psi, acc);
+                flush_queue<W>(a, di, n_q, q_ent, q_val, q_pos, mine, tile_keys, tile_psi, acc);
                 n_q = 0;
+                mine = 0;
             }
         }
         if (n_q > 0) {
             __builtin_amdgcn_wave_barrier();
-            flush_queue<W>(a, di, n_q, q_ent, q_val, tile_keys, tile_psi, acc);
+            flush_queue<W>(a, di, n_q, q_ent, q_val, q_pos, mine, tile_keys, tile_psi, acc);
         }
     }
     if (active) a.partial_rows[(int64_t)cb * a.n_sel + i] = acc;
