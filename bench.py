@@ -229,10 +229,11 @@ def summarize_trace(trace_csv, bench_out):
         ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         by.setdefault(name, []).append(ns)
     steps = res["steps"]
+    kernels = res["kernels"] if "kernels" in res else res["medium"]["kernels"]
     m = re.search(r"W=(\d)", res["config"]["workload"])
     W = m.group(1) if m else "1"
     out = []
-    for bench_name, k in res["kernels"].items():
+    for bench_name, k in kernels.items():
         n_last = int(round(k["launches_per_step"] * steps))
         fam = family(bench_name)
         want = [W if a == "W" else FANOUT.get(a, a) for a in _template_args(bench_name, fam)]
