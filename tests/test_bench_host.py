@@ -26,22 +26,45 @@ def test_template_args(bench):
     assert ta("f<Key<2>, 3>(x)", "f") == ["Key<2>", "3"]
 
 
-def test_recorded_traffic_matches_instantiation(bench):
+@pytest.mark.parametrize("workload,W", [("medium", 1), ("large", 2)])
+def test_recorded_traffic_matches_instantiation(bench, workload, W):
     path = os.path.join(ROOT, "profiles", "kernel_traffic.json")
-    rec = json.load(open(path))["kernels"]
+    rec = json.load(open(path))["workloads"][workload]["kernels"]
     fams = {e["family"] for e in rec.values()}
     assert {"gen_kernel", "bucket_kernel", "hist_kernel", "scatter_kernel", "emit_kernel"} <= fams
     # the two levels of the partition are told apart by their fan-out argument
-    lvl1 = bench.recorded_traffic("(hist_kernel<W, C::F1>)", 1)
-    lvl2 = bench.recorded_traffic("(hist_kernel<W, C::F2>)", 1)
+    lvl1 = bench.recorded_traffic("(hist_kernel<W, C::F1>)", W, workload)
+    lvl2 = bench.recorded_traffic("(hist_kernel<W, C::F2>)", W, workload)
     if lvl1 is not None and lvl2 is not None:
         names = [n for n, e in rec.items() if e["family"] == "hist_kernel"]
         by_arg = {bench._template_args(n, "hist_kernel")[1]: e for n, e in rec.items() if n in names}
         assert lvl1 == pytest.approx(by_arg["4096"]["read_bytes"] + by_arg["4096"]["write_bytes"])
         assert lvl2 == pytest.approx(by_arg["512"]["read_bytes"] + by_arg["512"]["write_bytes"])
     # a kernel without a record, and a width without one, give nothing
-    assert bench.recorded_traffic("no_such_kernel<W>", 1) is None
-    assert bench.recorded_traffic("bucket_kernel<W>", 7) is None
+    assert bench.recorded_traffic("no_such_kernel<W>", W, workload) is None
+    assert bench.recorded_traffic("bucket_kernel<W>", 7, workload) is None
+
+
+def test_summarize_trace_takes_the_timed_steps(bench, tmp_path, capsys):
+    # 2 timed steps of a kernel launched twice per step, after an untimed launch: the
+    # summary averages the last 4 dispatches only
+    rows = ["Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    durs = [9_000_000, 1_000_000, 2_000_000, 3_000_000, 4_000_000]
+    t = 0
+    for i, d in enumerate(durs):
+        rows.append(f'{i + 1},"void sci::emit_kernel<2>(sci::EmitArgs)",{t},{t + d}')
+        t += d + 10
+    csv_path = tmp_path / "trace.csv"
+    csv_path.write_text("\n".join(rows) + "\n")
+    res = {"metric": "m", "steps": 2, "config": {"workload": "large: W=2"},
+           "kernels": {"emit_kernel<W>": {"ms_per_launch": 2.5, "launches_per_step": 2.0}}}
+    out_path = tmp_path / "bench.out"
+    out_path.write_text("noise\n" + json.dumps(res) + "\n")
+    bench.summarize_trace(str(csv_path), str(out_path))
+    text = capsys.readouterr().out
+    line = [l for l in text.splitlines() if "emit_kernel<2>" in l][0]
+    cells = [c.strip() for c in line.strip("|").split("|")]
+    assert cells[1] == "4" and float(cells[2]) == pytest.approx(2.5) and float(cells[4]) == pytest.approx(5.0)
 
 
 def test_recorded_traffic_refuses_changed_source(bench, tmp_path, monkeypatch):
