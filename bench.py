@@ -66,8 +66,8 @@ def parse():
     ap.add_argument("--extras", default="whole,medium,select,screened,energy,batch",
                     help="comma list of extras (whole, medium, select, screened, energy, batch)")
     ap.add_argument("--large-sources", type=int, default=32768)
-    ap.add_argument("--large-chunk", type=int, default=1 << 30,
-                    help="pool chunk in candidates (0: time 2^28, 2^29, 2^30 once each and keep the fastest)")
+    ap.add_argument("--large-chunk", type=int, default=1 << 31,
+                    help="pool chunk in candidates (0: time 2^29, 2^30, 2^31 once each and keep the fastest)")
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_OUTPUT"),
@@ -120,7 +120,7 @@ def _template_args(name, fam):
 
 
 # fan-outs of the two partition levels as the compiled kernels spell them (DCfg<W>)
-FANOUT = {"C::F1": "4096", "C::F2": "512"}
+FANOUT = {1: {"C::F1": "4096", "C::F2": "512"}, 2: {"C::F1": "4096", "C::F2": "1024"}}
 
 
 def family(name):
@@ -135,7 +135,7 @@ def recorded_traffic(kernel_name, W, workload=None):
         return None
     rec = json.load(open(path))
     fam = family(kernel_name)
-    want = [str(W) if a == "W" else FANOUT.get(a, a) for a in _template_args(kernel_name, fam)]
+    want = [str(W) if a == "W" else FANOUT.get(int(W), {}).get(a, a) for a in _template_args(kernel_name, fam)]
     if "workloads" in rec:
         tables = [rec["workloads"].get(workload, {}).get("kernels", {})] if workload else \
             [w.get("kernels", {}) for w in rec["workloads"].values()]
@@ -236,7 +236,7 @@ def summarize_trace(trace_csv, bench_out):
     for bench_name, k in kernels.items():
         n_last = int(round(k["launches_per_step"] * steps))
         fam = family(bench_name)
-        want = [W if a == "W" else FANOUT.get(a, a) for a in _template_args(bench_name, fam)]
+        want = [W if a == "W" else FANOUT.get(int(W), {}).get(a, a) for a in _template_args(bench_name, fam)]
         for t, d_all in by.items():
             tn = t.split("(")[0].replace("void ", "") if "<" not in t.split("(")[0] else t
             if family(tn.split("(")[0].split("<")[0] + ("<" if "<" in t else "")) != fam and \
@@ -396,7 +396,7 @@ def large_chunk_sizes(torch, sci, ham, dets, sel, total, chunk):
         cur, nxt, n_cur, n_nxt = nxt, cur, n_nxt, n_cur
     torch.cuda.synchronize()
     sci.check_flags(flags, "chunk size pass")
-    del keys, hij, ws, set_a, set_b
+    del keys, hij, ws, set_a, set_b, cur, nxt, n_cur, n_nxt
     torch.cuda.empty_cache()
     return sizes
 
@@ -455,7 +455,7 @@ def large_headline(args, torch, sci, si, copy_gbps):
     chunk = args.large_chunk
     if chunk <= 0:  # sweep: one timed pass each after a warm-up pass
         sweep = {}
-        for c in (1 << 28, 1 << 29, 1 << 30):
+        for c in (1 << 29, 1 << 30, 1 << 31):
             ws, set_a, set_b, cap = buffers(c)
             run = lambda: (sci.sci_stream_dedup(ham, dets, n_src, 0, total, c, sel, n_in, set_a, set_b, cap, n_out,
                                                 ws, ws.numel(), flags, cur, dd), cur.wait_stream(dd))
@@ -468,8 +468,11 @@ def large_headline(args, torch, sci, si, copy_gbps):
         out["chunk_sweep_ms"] = {str(c): round(v, 1) for c, v in sweep.items()}
 
     sizes = None if args.counters else large_chunk_sizes(torch, sci, ham, dets, sel, total, chunk)
+    torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats(dev)
     ws, set_a, set_b, cap = buffers(chunk)
+    if sizes is not None and cap < sizes[-1]["m1"]:
+        raise SystemExit(f"set buffers of {cap} keys cannot hold the union of {sizes[-1]['m1']}")
 
     def step(ev):
         ev[0].record(cur)
@@ -702,7 +705,9 @@ def whole_extras(args, torch, sci, ham, sel):
     W = ham.W
     n_sel = sel.shape[0]
     total = n_sel * ham.n_coupled
-    chunk = args.large_chunk if args.large_chunk > 0 else 1 << 30
+    # chunks of 2^30: set buffers for the 5.5e9-key union (179 GB) leave no room for a
+    # 2^31 pool beside them
+    chunk = 1 << 30
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats(dev)
     ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)

@@ -42,11 +42,13 @@ struct DCfg {
     // samples per bucket, a wider spread, so their mean stays further below CAP
     static constexpr int TARGET = (W == 1) ? CAP * 3 / 8 : CAP / 4;
     static constexpr int F1 = 4096;                        // level-1 fan-out bound
-    static constexpr int F2 = 512;                         // level-2 fan-out bound
+    // level-2 fan-out bound: 1,024 for two-word keys, whose streamed pool chunks of 2^31
+    // candidates then keep final buckets of about 512 keys
+    static constexpr int F2 = (W == 1) ? 512 : 1024;
     // level-2 splitters: one workgroup sorts up to SCAP samples per level-1 bucket in
     // LDS (the whole of a CU's LDS for two-word keys), OVS2 samples per final bucket
     static constexpr int SCAP = (W == 1) ? 6144 : 4096;
-    static constexpr int OVS2 = SCAP / F2;                 // 12 W=1, 8 W=2
+    static constexpr int OVS2 = SCAP / F2;                 // 12 W=1, 4 W=2
     static constexpr int M1 = 65536;                       // level-1 sample bound
     static constexpr int64_t TILE1 = 131072;               // keys per level-1 tile
     static constexpr int64_t TILE2 = 16384;                // keys per level-2 tile
@@ -1752,7 +1754,7 @@ struct WsLayout {
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 template <int W>
-static WsLayout ws_layout(int64_t n) {
+static WsLayout ws_layout(int64_t n, bool cand_scratch = false) {
     using C = DCfg<W>;
     WsLayout L{};
     const int64_t nn = std::max<int64_t>(n, 1);
@@ -1769,7 +1771,7 @@ static WsLayout ws_layout(int64_t n) {
         return o;
     };
     L.bufA = take((size_t)nn * W * 8);
-    L.bufB = take((size_t)nn * W * 8);
+    L.bufB = cand_scratch ? 0 : take((size_t)nn * W * 8);
     L.ids = take((size_t)nn * 2);
     L.segA = take((size_t)(S2 + 1) * 8);
     L.segB = take((size_t)(S2 + 1) * 8);
@@ -1819,11 +1821,12 @@ template <int W>
 static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_in, const int64_t *n_set_in,
                           uint64_t *set_out, int64_t *n_set_out, int64_t set_cap, uint64_t *novel,
                           int64_t *n_novel, int64_t novel_cap, char *ws, uint32_t *flags, hipStream_t st,
-                          bool check_set) {
+                          bool check_set, bool cand_scratch) {
     using C = DCfg<W>;
-    const WsLayout L = ws_layout<W>(n);
+    const WsLayout L = ws_layout<W>(n, cand_scratch);
     uint64_t *bufA = (uint64_t *)(ws + L.bufA);
-    uint64_t *bufB = (uint64_t *)(ws + L.bufB);
+    // the second level writes over the candidates when they may be overwritten
+    uint64_t *bufB = cand_scratch ? const_cast<uint64_t *>(cand) : (uint64_t *)(ws + L.bufB);
     int64_t *segA = (int64_t *)(ws + L.segA);
     int64_t *segB = (int64_t *)(ws + L.segB);
     int64_t *counts = (int64_t *)(ws + L.counts);
@@ -2007,12 +2010,24 @@ extern "C" size_t sci_dedup_workspace_bytes(int32_t n_words, int64_t n_cand) {
 
 namespace sci {
 
-// sci_dedup_merge with the strict-order check of set_in optional: callers that pass a
-// set this library produced skip the extra pass over it.
+// Workspace of one dedup call; with cand_scratch the candidate buffer itself takes the
+// second partition level's output (the streaming loop's pool chunk, free once the
+// first level has read it), so one key buffer fewer is needed.
+size_t dedup_ws_bytes(int32_t n_words, int64_t n_cand, bool cand_scratch) {
+    if (n_cand < 0) return 0;
+    if (n_words == 1) return ws_layout<1>(n_cand, cand_scratch).total;
+    if (n_words == 2) return ws_layout<2>(n_cand, cand_scratch).total;
+    return 0;
+}
+
+// sci_dedup_merge with the strict-order check of set_in optional (callers that pass a
+// set this library produced skip the extra pass over it) and, for callers that own
+// the candidate buffer, its reuse as scratch.
 int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
                             const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
                             uint64_t *novel, int64_t *n_novel, int64_t novel_capacity, void *workspace,
-                            size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in) {
+                            size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in,
+                            bool cand_scratch) {
     set_error("");
     if (n_words < 1 || n_words > SCI_MAX_WORDS)
         return fail(n_words < 1 ? SCI_EINVAL : SCI_EUNSUPPORTED, "sci_dedup_merge: n_words=%d", n_words);
@@ -2026,14 +2041,14 @@ int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_can
         return fail(SCI_EINVAL, "sci_dedup_merge: set_out aliases an input");
     if (n_cand >= (1ll << 32))
         return fail(SCI_EUNSUPPORTED, "sci_dedup_merge: %lld candidates exceed one call", (long long)n_cand);
-    const size_t need = sci_dedup_workspace_bytes(n_words, n_cand);
+    const size_t need = dedup_ws_bytes(n_words, n_cand, cand_scratch);
     if (workspace_bytes < need)
         return fail(SCI_ECAPACITY, "sci_dedup_merge: workspace %zu < %zu bytes", workspace_bytes, need);
     if (n_words == 1)
         return dedup_impl<1>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                             novel_capacity, (char *)workspace, dev_flags, st, check_set_in);
+                             novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch);
     return dedup_impl<2>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                         novel_capacity, (char *)workspace, dev_flags, st, check_set_in);
+                         novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch);
 }
 
 }  // namespace sci

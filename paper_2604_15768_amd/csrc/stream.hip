@@ -3,8 +3,10 @@
 //
 // Two pool buffers hold consecutive chunks of candidates.  Generation of chunk
 // k+1 (gen stream) overlaps the de-duplication and merge of chunk k (dedup
-// stream); events order each buffer's reuse.  Set sizes never leave the
-// device, so the loop needs no host synchronisation.
+// stream); events order each buffer's reuse.  The dedup of a chunk writes its
+// second partition level back into the chunk's own pool buffer (consumed by the
+// first level), so the dedup workspace holds one key buffer.  Set sizes never
+// leave the device, so the loop needs no host synchronisation.
 #include <vector>
 
 #include "sci_internal.hpp"
@@ -31,7 +33,7 @@ static StreamLayout stream_layout(int W, int64_t chunk) {
     L.n_run = off;
     off += 256;
     L.dedup = off;
-    off += sci_dedup_workspace_bytes(W, chunk);
+    off += dedup_ws_bytes(W, chunk, true);
     L.total = off;
     return L;
 }
@@ -125,7 +127,7 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         // caller's set_in needs the order check
         st = dedup_merge_checked(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
                                  set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup,
-                                 dev_flags, sd, /*check_set_in=*/k == 0);
+                                 dev_flags, sd, /*check_set_in=*/k == 0, /*cand_scratch=*/true);
         if (st != SCI_OK) break;
         SCI_HIP_TRY(hipEventRecord(ready[b], sd));
         int64_t *n_run = (int64_t *)(ws + L.n_run);

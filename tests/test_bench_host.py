@@ -38,8 +38,9 @@ def test_recorded_traffic_matches_instantiation(bench, workload, W):
     if lvl1 is not None and lvl2 is not None:
         names = [n for n, e in rec.items() if e["family"] == "hist_kernel"]
         by_arg = {bench._template_args(n, "hist_kernel")[1]: e for n, e in rec.items() if n in names}
+        f2 = "512" if W == 1 else "1024"
         assert lvl1 == pytest.approx(by_arg["4096"]["read_bytes"] + by_arg["4096"]["write_bytes"])
-        assert lvl2 == pytest.approx(by_arg["512"]["read_bytes"] + by_arg["512"]["write_bytes"])
+        assert lvl2 == pytest.approx(by_arg[f2]["read_bytes"] + by_arg[f2]["write_bytes"])
     # a kernel without a record, and a width without one, give nothing
     assert bench.recorded_traffic("no_such_kernel<W>", W, workload) is None
     assert bench.recorded_traffic("bucket_kernel<W>", 7, workload) is None
