@@ -1640,7 +1640,14 @@ void emit_kernel(EmitArgs a) {
         for (int qw = 0; qw < nw; ++qw) {
             const int64_t c0 = (w0 + qw) * kEmitStep;
             const int64_t c1 = c0 + kEmitStep < total ? c0 + kEmitStep : total;
-            const int64_t i1 = s_cut[qw];
+            // A split search returns a cut in [max(0, c1 - nBs), min(c1, nA)] for any data,
+            // and for sorted inputs consecutive cuts differ by 0..win.  Clamping to that
+            // step keeps na, nb in [0, win] (the LDS window) and every load in range
+            // even when an unsorted set (flagged by the order check) breaks monotony;
+            // for sorted inputs it changes nothing.
+            const int64_t win64 = c1 - c0;
+            int64_t i1 = s_cut[qw];
+            i1 = i1 < i0 ? i0 : (i1 > i0 + win64 ? i0 + win64 : i1);
             const int64_t j0 = c0 - i0;
             const int na = (int)(i1 - i0), nb = (int)((c1 - i1) - j0);
             for (int t = threadIdx.x; t < na; t += kDThreads) sA[t] = load_key<W>(A, i0 + t);

@@ -336,6 +336,34 @@ def test_dedup_flags():
     assert sci.check_flags(flags2, "dedup", allow=sci.FLAG_UNSORTED) & sci.FLAG_UNSORTED
 
 
+@pytest.mark.parametrize("W", [1, 2])
+def test_dedup_unsorted_set_against_large_runs(W):
+    """A set passed out of order is flagged, and the merge stays inside its buffers even
+    where a unit's run exceeds LDS (windowed merge, whose split points are not monotone
+    for such a set); the same inputs with the set in order then give the oracle's union."""
+    import torch
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(110 + W))
+    heavy = rng.integers(1 << 40, 1 << 62, size=W, dtype=np.int64).astype(np.uint64)
+    d = 40_000
+    offs = np.concatenate([-1 - np.arange(d), 1 + np.arange(d)]).astype(np.int64)
+    near = np.repeat(heavy[None, :], 2 * d, axis=0)
+    near[:, 0] = (near[:, 0].astype(np.int64) + offs).astype(np.uint64)
+    spread = _random_keys(rng, 300_000, W, pool=200_000)
+    cand = np.concatenate([np.repeat(heavy[None, :], 400_000, axis=0), near, spread])
+    cand = cand[rng.permutation(cand.shape[0])]
+    setin = si.sort_keys(np.concatenate([near[::5], spread[::3], _random_keys(rng, 5000, W, pool=5000)]))
+    setin = setin[np.concatenate([[True], np.any(setin[1:] != setin[:-1], axis=1)])]
+    say(f"dedup unsorted set W={W} n={cand.shape[0]} set={setin.shape[0]}")
+    c = sci.keys_to_device(cand)
+    for order in (setin[::-1], setin[rng.permutation(setin.shape[0])]):
+        out, n_out, nov, n_nov, flags = sci.dedup_merge(c, sci.keys_to_device(np.ascontiguousarray(order)), W,
+                                                        want_novel=True)
+        torch.cuda.synchronize()
+        assert sci.check_flags(flags, "dedup", allow=sci.FLAG_UNSORTED | sci.FLAG_OVERFLOW) & sci.FLAG_UNSORTED
+    _dedup_check(sci, cand, setin, W)
+
+
 # ---------------------------------------------------------------------------
 # energy
 # ---------------------------------------------------------------------------
