@@ -45,10 +45,12 @@ struct DCfg {
     // level-2 fan-out bound: 1,024 for two-word keys, whose streamed pool chunks of 2^31
     // candidates then keep final buckets of about 512 keys
     static constexpr int F2 = (W == 1) ? 512 : 1024;
-    // level-2 splitters: one workgroup sorts up to SCAP samples per level-1 bucket in
-    // LDS (the whole of a CU's LDS for two-word keys), OVS2 samples per final bucket
+    // level-2 splitters: one workgroup per level-1 bucket sorts its samples in LDS, up
+    // to SCAP at once (the whole of a CU's LDS for two-word keys); two-word keys sort
+    // two such runs (MS2 samples in all), 8 per final bucket against 12 for one word
     static constexpr int SCAP = (W == 1) ? 6144 : 4096;
-    static constexpr int OVS2 = SCAP / F2;                 // 12 W=1, 4 W=2
+    static constexpr int MS2 = (W == 1) ? SCAP : 2 * SCAP;  // level-2 sample bound
+    static constexpr int OVS2 = MS2 / F2;                  // 12 W=1, 8 W=2
     static constexpr int M1 = 65536;                       // level-1 sample bound
     static constexpr int64_t TILE1 = 131072;               // keys per level-1 tile
     static constexpr int64_t TILE2 = 16384;                // keys per level-2 tile
@@ -366,7 +368,11 @@ __device__ __forceinline__ int64_t sample_pos(int64_t start, int64_t size, int64
 }
 
 // One workgroup per input segment: choose the fan-out, draw one sample per
-// stratum, sort them, pick splitters at equal sample ranks.
+// stratum, sort them, pick splitters at equal sample ranks.  Above one LDS load
+// of samples (two-word keys at level 2), the first half of the strata is sorted
+// and set aside while the second half is sorted, then loaded beside it; the
+// sample of merged rank r is found by a merge-path search over the two runs,
+// which gives the keys one sort of all samples would give.
 template <int W>
 __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     using C = DCfg<W>;
@@ -380,20 +386,46 @@ __global__ __launch_bounds__(kDThreads) void splitter_kernel(LevelArgs a) {
     if (threadIdx.x == 0) a.fan[s] = f;
     if (f == 1) return;
     const int64_t M = std::min<int64_t>(size, std::min<int64_t>((int64_t)a.ovs * f, a.max_samples));
-    if (M > C::SCAP) return;  // cannot happen: the host sorts larger samples in runs
+    if (M > 2 * C::SCAP) return;  // cannot happen: the host sorts larger samples in runs
     uint64_t *sp = a.spl + (int64_t)s * (a.F - 1) * W;
-    for (int64_t k = threadIdx.x; k < M; k += kDThreads) {
-        s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k, M));
+    // one run, or two of M/2 and M - M/2 samples; the first of two waits in this
+    // segment's part of the level's output (at least M keys, written only by the
+    // scatter pass that follows) while the second is sorted
+    const int n_runs = M > C::SCAP ? 2 : 1;
+    const int nA = n_runs == 2 ? (int)(M / 2) : 0, nB = (int)(M - nA);
+    uint64_t *stage = a.out + start * W;
+    const Key<W> *B = nullptr;
+    for (int run = 0; run < n_runs; ++run) {
+        const int k0 = run == n_runs - 1 ? nA : 0, m = run == n_runs - 1 ? nB : nA;
+        for (int k = threadIdx.x; k < m; k += kDThreads)
+            s_buf[k] = load_key<W>(a.in, sample_pos(start, size, k0 + k, M));
+        __syncthreads();
+        const Key<W> ref = s_buf[0];
+        __syncthreads();
+        Key<W> orkey;
+        const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, R, &orkey);
+        B = lds_radix_sort<W, C::SCAP>(s_buf, s_tmp, m, nbits, orkey, R);
+        if (run < n_runs - 1) {
+            for (int i = threadIdx.x; i < m; i += kDThreads) store_key<W>(stage, i, B[i]);
+            __syncthreads();  // both LDS buffers are reused by the next run
+        }
     }
+    Key<W> *A = (B == s_buf) ? s_tmp : s_buf;
+    for (int i = threadIdx.x; i < nA; i += kDThreads) A[i] = load_key<W>(stage, i);
     __syncthreads();
-    const Key<W> ref = s_buf[0];
-    __syncthreads();
-    Key<W> orkey;
-    const int nbits = block_varying_bits<W>(M, ref, [&](int64_t i) { return s_buf[i]; }, R, &orkey);
-    Key<W> *res = lds_radix_sort<W, C::SCAP>(s_buf, s_tmp, (int)M, nbits, orkey, R);
     for (int j = threadIdx.x; j < f - 1; j += kDThreads) {
-        const int64_t r = ((int64_t)(j + 1) * M) / f;
-        store_key<W>(sp, j, res[r]);
+        const int r = (int)(((int64_t)(j + 1) * M) / f);  // 0 < r < M
+        // i = keys of A among the first r of the merge (equal keys: A first); with one
+        // run A is empty and the pick is B[r]
+        int lo = r > nB ? r - nB : 0, hi = r < nA ? r : nA;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (!key_less<W>(B[r - mid - 1], A[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        const int i = lo, jb = r - lo;
+        const bool takeA = i < nA && (jb >= nB || !key_less<W>(B[jb], A[i]));
+        store_key<W>(sp, j, takeA ? A[i] : B[jb]);
     }
 }
 
@@ -1901,7 +1933,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             } else {
                 a.target = C::TARGET;
                 a.ovs = C::OVS2;
-                a.max_samples = C::SCAP;
+                a.max_samples = C::MS2;
                 a.fan = (int32_t *)(ws + L.fan2);
                 a.spl = (uint64_t *)(ws + L.spl2);
             }
