@@ -1146,23 +1146,32 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
 
 // Three workgroups per CU: LDS holds 2 x 24 KB of keys for each (3,072 one-word or
 // 1,536 two-word keys), and at most 80 VGPRs leave room for their 24 waves.
+//
+// The running set's keys of the unit's range are looked up in the unit's hash table
+// before anything is sorted: a short range is streamed through the table (its first
+// loads issued together with the unit's own keys), a long one is searched per
+// distinct key.  Only the keys the set does not hold are compacted, sorted and
+// written, so the run handed to emit is disjoint from the set and the sort skips
+// every key the set already holds.
 template <int W>
 __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(6, 8)))
 void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
-    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's unique keys
+    constexpr int kSP = 2;                                      // set keys per thread loaded up front
+    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's novel keys
     __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
     __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];  // per-wave digit counts, then output offsets
+    __shared__ uint32_t s_dup[C::CAP / 32];  // bit i: the key at position i is a set key
     __shared__ uint64_t s_or[2];
     __shared__ int s_u[kBWaves];
-    __shared__ int64_t s_wsum[kBWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t s = blockIdx.x;  // unit
     if (s >= *a.n_units) return;
     int64_t start, size;
     unit_span(a, s, start, size);
     const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
+    const int64_t nb = bh - bl;
 
     if (size > C::CAP) {
         // sorted by bucket_big_kernel
@@ -1186,6 +1195,17 @@ void bucket_kernel(BucketArgs a) {
             const int i = my0 + k * kWave + lane;
             if (k < Km && i < m) kk[k] = load_key<W>(a.src, start + i);
         }
+        // a set range up to 56 keys per unit key is streamed through the hash table;
+        // its first kSP x 512 keys are in flight with the unit's own
+        const bool stream_set = nb > 0 && nb <= 56 * (int64_t)m;
+        Key<W> sk[kSP];
+        if (stream_set) {
+#pragma unroll
+            for (int p = 0; p < kSP; ++p) {
+                const int64_t j = bl + p * kBThreads + threadIdx.x;
+                if (j < bh) sk[p] = load_key<W>(a.B, j);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kBK; ++k) {
             const int i = my0 + k * kWave + lane;
@@ -1197,6 +1217,7 @@ void bucket_kernel(BucketArgs a) {
         const uint32_t tmask = (1u << log_t) - 1u;
         uint32_t *tab = reinterpret_cast<uint32_t *>(s_k1);
         for (int i = threadIdx.x; i < (1 << log_t) / 2; i += kBThreads) tab[i] = 0xffffffffu;
+        for (int i = threadIdx.x; i < C::CAP / 32; i += kBThreads) s_dup[i] = 0u;
         if (threadIdx.x == 0) s_or[0] = s_or[1] = 0;
         __syncthreads();
         const Key<W> ref = s_k0[0];
@@ -1225,8 +1246,50 @@ void bucket_kernel(BucketArgs a) {
                 h = (h + 1u) & tmask;
             }
         }
-        __syncthreads();  // all probes done: keys may move
-        // each wave compacts its first occurrences to the front of its own slice
+        __syncthreads();  // the table is complete (and read-only from here)
+        if (nb > 0) {
+            if (stream_set) {
+                // a set key found in the table marks the unit key that holds the slot; the
+                // table is at most half full, so every walk reaches an empty slot
+                auto mark = [&](const Key<W> &key) {
+                    uint32_t h = key_hash<W>(key, log_t);
+                    while (true) {
+                        const uint32_t cur = tab[h >> 1];
+                        const uint32_t v = (h & 1u) ? (cur >> 16) : (cur & 0xffffu);
+                        if (v == 0xffffu) return;
+                        if (key_eq<W>(s_k0[v], key)) {
+                            atomicOr(&s_dup[v >> 5], 1u << (v & 31));
+                            return;
+                        }
+                        h = (h + 1u) & tmask;
+                    }
+                };
+#pragma unroll
+                for (int p = 0; p < kSP; ++p)
+                    if (bl + p * kBThreads + threadIdx.x < bh) mark(sk[p]);
+                for (int64_t j0 = bl + kSP * kBThreads; j0 < bh; j0 += kSP * kBThreads) {
+#pragma unroll
+                    for (int p = 0; p < kSP; ++p) {
+                        const int64_t j = j0 + p * kBThreads + threadIdx.x;
+                        if (j < bh) sk[p] = load_key<W>(a.B, j);
+                    }
+#pragma unroll
+                    for (int p = 0; p < kSP; ++p)
+                        if (j0 + p * kBThreads + threadIdx.x < bh) mark(sk[p]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kBK; ++k) {
+                    if (k >= Km) break;  // wave-uniform
+                    const int i = my0 + k * kWave + lane;
+                    if (((fresh >> k) & 1u) && contains_set<W>(a.B, bl, bh, kk[k]))
+                        atomicOr(&s_dup[i >> 5], 1u << (i & 31));
+                }
+            }
+            __syncthreads();
+        }
+        // each wave compacts its novel keys (first occurrences the set does not hold)
+        // to the front of its own slice
         int uw = 0;
         uint64_t acc[W];
 #pragma unroll
@@ -1235,7 +1298,7 @@ void bucket_kernel(BucketArgs a) {
         for (int k = 0; k < kBK; ++k) {
             if (k >= Km) break;  // wave-uniform
             const int i = my0 + k * kWave + lane;
-            const bool keep = (i < m) && ((fresh >> k) & 1u);
+            const bool keep = (i < m) && ((fresh >> k) & 1u) && !((s_dup[i >> 5] >> (i & 31)) & 1u);
             Key<W> key;
             if (keep) {
                 key = kk[k];
@@ -1265,20 +1328,20 @@ void bucket_kernel(BucketArgs a) {
 #pragma unroll
         for (int ww = 0; ww < kBWaves; ++ww) u += s_u[ww];
 
-        // stable LSD radix sort of the u unique keys, LDS resident.  The first pass
+        // stable LSD radix sort of the u novel keys, LDS resident.  The first pass
         // reads every wave's own slice (any starting order is fine); later passes
         // read the contiguous result of the previous pass.
         Key<W> *cur = s_k0, *nxt = s_k1;
         const int Kd = (u + kBThreads - 1) / kBThreads;
         const int CHd = Kd * kWave;
         bool first = true;
-        // digits cover only the bits that vary in this unit; a window in which no key
-        // differs would be an identity pass and is skipped
+        // digits cover only the bits that vary among the novel keys; a window in which
+        // no key differs would be an identity pass and is skipped
         for (int shift = lo_bit; shift < nbits; shift += 8) {
             const uint32_t vm = digit_of<W>(orkey, shift);  // varying bits of this window
             if (vm == 0u) continue;                         // workgroup-uniform
             const int base_pos = first ? my0 : w * CHd;
-            const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's uniques
+            const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's keys
             const int limit = first ? my0 + uw : u;
             unit_radix_pass<W, kBK>(cur, nxt, shift, vm, base_pos, rounds, limit, s_cnt);
             Key<W> *t = cur;
@@ -1287,7 +1350,7 @@ void bucket_kernel(BucketArgs a) {
             first = false;
         }
         if (first) {
-            // no pass ran: every unique key is equal, so there is exactly one
+            // no pass ran: at most one novel key (distinct keys differ somewhere)
             if (threadIdx.x == 0) {
                 for (int ww = 0; ww < kBWaves; ++ww)
                     if (s_u[ww] > 0) {
@@ -1298,13 +1361,17 @@ void bucket_kernel(BucketArgs a) {
             __syncthreads();
             cur = s_k1;
         }
-        finish_unit<W>(a, s, cur, u, start, bl, bh, reinterpret_cast<uint32_t *>(cur == s_k0 ? s_k1 : s_k0),
-                       s_wsum);
+        for (int i = threadIdx.x; i < u; i += kBThreads) store_key<W>(a.dst, start + i, cur[i]);
+        if (threadIdx.x == 0) {
+            a.nuniq[s] = u;
+            a.ucount[s] = u + nb;
+            a.ncount[s] = u;
+        }
         return;
     }
     if (threadIdx.x == 0) {  // an empty unit: its range holds only set keys
         a.nuniq[s] = 0;
-        a.ucount[s] = bh - bl;
+        a.ucount[s] = nb;
         a.ncount[s] = 0;
     }
 }
