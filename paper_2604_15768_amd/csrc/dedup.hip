@@ -656,9 +656,12 @@ __global__ __launch_bounds__(kSThreads) void scatter_kernel(LevelArgs a) {
     // point refuses larger inputs), so 32 bits hold them and the LDS stays small
     __shared__ uint32_t s_cur[FMAX];
     // a small persistent grid walks the tiles: every workgroup keeps one open output
-    // run per bucket, and fewer runs in flight at once merge better in the caches
+    // run per bucket, and fewer runs in flight at once merge better in the caches.
+    // A bucket's runs of consecutive tiles are adjacent in the output and share their
+    // boundary lines, so each round of gridDim tiles is dealt out XCD by XCD: those
+    // lines are then written through one L2 instead of two.
     const int64_t n_tiles = a.tile_base[a.S_in];
-    for (int64_t g = blockIdx.x; g < n_tiles; g += gridDim.x) {
+    for (int64_t g = xcd_local_block(blockIdx.x, gridDim.x); g < n_tiles; g += gridDim.x) {
         __syncthreads();  // the previous tile's cursors are no longer read
         const int s = find_segment(a.tile_base, a.S_in, g);
         const int64_t t = g - a.tile_base[s];

@@ -429,18 +429,8 @@ __device__ __forceinline__ void gen_source(const GenArgs &a, const int64_t src, 
     }
 }
 
-// Workgroups are dispatched to the 8 XCDs of the chip in turn, and each XCD has its
-// own L2.  Workgroup b (on XCD b % 8) takes source x*q + min(x, r) + b/8, with
-// q, r = n / 8, n % 8: every XCD walks one contiguous range of sources, so
-// neighbouring sources (sorted keys share most integral rows) meet in one L2.
-// The map is a bijection on [0, n) whatever the dispatch order.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int64_t xcd_local_block(int64_t b, int64_t n) {
-    const int64_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
-    return x * q + (x < r ? x : r) + b / kXcds;
-}
-
+// Sources are taken XCD by XCD (xcd_local_block): neighbouring sources (sorted keys
+// share most integral rows) meet in one L2.
 template <int W, bool DENSE>
 __global__ __launch_bounds__(kGenThreads) void gen_kernel(GenArgs a) {
     __shared__ GenLds L;

@@ -16,6 +16,17 @@ namespace sci {
 
 constexpr int kWave = 64;
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn, and each XCD has its
+// own L2.  Workgroup b (on XCD b % 8) of n gets index x*q + min(x, r) + b/8, with
+// q, r = n / 8, n % 8: every XCD takes one contiguous range of [0, n).  The map is a
+// bijection on [0, n) whatever the dispatch order.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_local_block(int64_t b, int64_t n) {
+    const int64_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // Hamiltonian handle: integrals and the tables the kernels read, all device.
 // ---------------------------------------------------------------------------
