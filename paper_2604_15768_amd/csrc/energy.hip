@@ -189,17 +189,42 @@ __device__ double diag_elem(const EnergyArgs &a, const Key<W> &d) {
 // Off-diagonal part of (H psi)_i for the rows of blockIdx.x against the
 // columns of column block blockIdx.y; the partial sum goes to
 // partial_rows[blockIdx.y][i] (combined in a fixed order by hpsi_finish_kernel).
-// Connected pairs found by a wave wait in a per-wave LDS queue, in ascending
-// column order, and are evaluated 64 at a time with every lane busy (one
-// entry per lane, the row's determinant fetched from its owner lane); each row
-// lane then adds its own entries in queue order (their positions, recorded as
-// they were queued), so every row still sums its terms in ascending j.
+//
+// Screening is a dense contraction.  With each determinant read as a 0/1 vector
+// over the 2n spin orbitals, D_i XOR D_j has 2N - 2 <D_i, D_j> set bits when both
+// hold N electrons, so the pair is connected (two or four bits) exactly when the
+// overlap is N - 1 or N - 2.  Each wave computes the overlaps of its 64 rows with 32
+// columns at a time by 8-bit matrix-core products (32 x 32 x 32 per instruction,
+// the bits expanded to bytes), accumulating from 2 - N so that a connected pair
+// reads 0 or 1.  Connected pairs wait in a per-wave LDS queue and are evaluated
+// 64 at a time with every lane busy (one entry per lane, the row's determinant
+// fetched from its owner lane, the excitation rebuilt from the exact XOR).  The
+// pairs of one row and one group of 32 columns are consecutive in the queue, in
+// ascending column order; the row lane records each such segment and adds its
+// entries in queue order, so every row still sums its terms in ascending j.
 constexpr int kQueue = 2 * kWave;
-constexpr int kSlots = 8;  // queued entries per row lane before the queue is flushed
+constexpr int kSlots = 8;  // queue segments per row lane before the queue is flushed
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// bits [32c + 16g, 32c + 16g + 16) of a key, bit b to byte b (0 or 1) of the result
+template <int W, int C>
+__device__ __forceinline__ v4i key_bytes16(const Key<W> &k, int g) {
+    const uint32_t x = (uint32_t)(k.w[C / 2] >> (32 * (C % 2) + 16 * g)) & 0xffffu;
+    v4i r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        // nibble bits 0..3 land on bits 0, 8, 16, 24: the four shifted copies occupy
+        // disjoint bit ranges, so the product has no carries
+        r[d] = (int)((((x >> (4 * d)) & 15u) * 0x00204081u) & 0x01010101u);
+    }
+    return r;
+}
 
 template <int W>
 __device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &di, int n_q, const uint32_t *q_ent,
-                                           double *q_val, const uint8_t *q_pos, int mine, const Key<W> *tile_keys,
+                                           double *q_val, const uint16_t *q_seg, int mine, const Key<W> *tile_keys,
                                            const double *tile_psi, double &acc) {
     const int lane = threadIdx.x & (kWave - 1);
     for (int base = 0; base < n_q; base += kWave) {
@@ -211,16 +236,22 @@ __device__ __forceinline__ void flush_queue(const EnergyArgs &a, const Key<W> &d
         for (int j = 0; j < W; ++j) bra.w[j] = __shfl(di.w[j], r);
         if (k < n_q) {
             const int t = (int)(e & 0x3ffu);
-            const int pc = (e >> 15) & 1u ? 4 : 2;
             const Key<W> ket = tile_keys[t];
             Key<W> x;
 #pragma unroll
             for (int j = 0; j < W; ++j) x.w[j] = bra.w[j] ^ ket.w[j];
-            q_val[k] = offdiag_elem<W>(a, bra, ket, x, pc) * tile_psi[t];
+            // the overlap test is exact for determinants of N electrons; others (flagged)
+            // can pass it without being connected and contribute nothing
+            const int pc = key_popc<W>(x);
+            q_val[k] = (pc == 2 || pc == 4) ? offdiag_elem<W>(a, bra, ket, x, pc) * tile_psi[t] : 0.0;
         }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int j = 0; j < mine; ++j) acc += q_val[q_pos[lane * kSlots + j]];
+    for (int j = 0; j < mine; ++j) {
+        const uint32_t sg = q_seg[lane * kSlots + j];
+        const int k0 = (int)(sg & 0xffu), k1 = k0 + (int)(sg >> 8);
+        for (int k = k0; k < k1; ++k) acc += q_val[k];
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -228,9 +259,9 @@ template <int W>
 struct HpsiLds {
     Key<W> tile_keys[kColTile];
     double tile_psi[kColTile];
-    uint32_t ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | (four moved << 15) | column
+    uint32_t ent[kRowThreads / kWave][kQueue];  // (row lane << 16) | column
     double val[kRowThreads / kWave][kQueue];
-    uint8_t pos[kRowThreads / kWave][kWave * kSlots];  // queue positions of each row lane's entries
+    uint16_t seg[kRowThreads / kWave][kWave * kSlots];  // each row lane's queue segments: start | count << 8
 };
 
 // rows [rb*256, rb*256+256) against column block cb of n_col
@@ -239,7 +270,7 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
     Key<W> *tile_keys = S.tile_keys;
     double *tile_psi = S.tile_psi;
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1), w = tid / kWave;
+    const int lane = tid & (kWave - 1), w = tid / kWave, g = lane >> 5;
     const int64_t i = rb * kRowThreads + tid;
     const bool active = i < a.n_sel;
     Key<W> di;
@@ -256,9 +287,36 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
                 atomicOr(a.flags, SCI_FLAG_UNSORTED);
         }
     }
+    const uint64_t act = __ballot(active);
+    // 32-bit chunks of the key that hold spin orbitals (2n bits)
+    constexpr int kCh = 2 * W;
+    const int nch = (2 * a.n + 31) / 32 < kCh ? (2 * a.n + 31) / 32 : kCh;
+    const int bias = 2 - (a.na + a.nb);
+    // matrix-core operands of this wave's rows: half h holds rows 32h .. 32h+31, lane
+    // l the row 32h + l%32 and bytes 16 (l/32) .. +15 of each chunk.  They are rebuilt
+    // after every queue flush, so their registers are free while the queue is evaluated.
+    v4i fa[2][kCh];
+    auto build_rows = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            Key<W> rk;
+#pragma unroll
+            for (int j = 0; j < W; ++j) rk.w[j] = __shfl(di.w[j], 32 * h + (lane & 31));
+#pragma unroll
+            for (int c = 0; c < kCh; ++c) {
+                if (c == 0) fa[h][c] = key_bytes16<W, 0>(rk, g);
+                if (c == 1) fa[h][c] = key_bytes16<W, 1>(rk, g);
+                if constexpr (kCh > 2) {
+                    if (c == 2) fa[h][c] = key_bytes16<W, (kCh > 2 ? 2 : 0)>(rk, g);
+                    if (c == 3) fa[h][c] = key_bytes16<W, (kCh > 2 ? 3 : 0)>(rk, g);
+                }
+            }
+        }
+    };
+    build_rows();
     uint32_t *q_ent = S.ent[w];
     double *q_val = S.val[w];
-    uint8_t *q_pos = S.pos[w];
+    uint16_t *q_seg = S.seg[w];
     const int64_t per = ceil_div_dev(ceil_div_dev(a.n_sel, (int64_t)n_col), (int64_t)kColTile) * kColTile;
     const int64_t c0 = (int64_t)cb * per;
     const int64_t c1 = min<int64_t>(c0 + per, a.n_sel);
@@ -288,33 +346,82 @@ __device__ __forceinline__ void hpsi_tile(const EnergyArgs &a, int64_t rb, int c
         }
         __syncthreads();
         int n_q = 0;   // wave-uniform
-        int mine = 0;  // this row lane's queued entries
-        for (int t = 0; t < cnt; ++t) {
-            const Key<W> dj = tile_keys[t];
-            Key<W> x;
+        int mine = 0;  // this row lane's queue segments
+        for (int t0 = 0; t0 < cnt; t0 += 32) {
+            const int t = t0 + (lane & 31);
+            const bool tv = t < cnt;
+            const Key<W> ck = tile_keys[tv ? t : 0];
+            // Columns are the first operand and rows the second: accumulator r of product h
+            // holds row 32h + l%32 against column t0 + 8(r/4) + 4(l/32) + r%4.  Each lane
+            // gathers, per product, its 16 columns' tests into a mask at their column bits.
+            // The two products run one after the other through the same accumulators.
+            uint32_t mh[2];
 #pragma unroll
-            for (int j = 0; j < W; ++j) x.w[j] = di.w[j] ^ dj.w[j];
-            const int pc = key_popc<W>(x);
-            const bool conn = active && (pc == 2 || pc == 4);
-            const uint64_t bal = __ballot(conn);
-            if (bal == 0ull) continue;
-            if (conn) {
-                const int p = n_q + __popcll(bal & lanemask_lt());
-                q_ent[p] = ((uint32_t)lane << 16) | ((uint32_t)(pc == 4) << 15) | (uint32_t)t;
-                q_pos[lane * kSlots + mine] = (uint8_t)p;
-                ++mine;
+            for (int h = 0; h < 2; ++h) {
+                v16i ov;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) ov[r] = bias;
+#pragma unroll
+                for (int c = 0; c < kCh; ++c) {
+                    if (c >= nch) break;
+                    v4i fb;
+                    if (c == 0) fb = key_bytes16<W, 0>(ck, g);
+                    if (c == 1) fb = key_bytes16<W, 1>(ck, g);
+                    if constexpr (kCh > 2) {
+                        if (c == 2) fb = key_bytes16<W, (kCh > 2 ? 2 : 0)>(ck, g);
+                        if (c == 3) fb = key_bytes16<W, (kCh > 2 ? 3 : 0)>(ck, g);
+                    }
+                    ov = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb, fa[h][c], ov, 0, 0, 0);
+                }
+                uint32_t m = 0u;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) m |= ((uint32_t)ov[r] < 2u ? 1u : 0u) << (8 * (r >> 2) + (r & 3));
+                mh[h] = m << (4 * g);
             }
-            n_q += __popcll(bal);
-            if (n_q >= kWave || __ballot(mine >= kSlots) != 0ull) {
-                __builtin_amdgcn_wave_barrier();
-                flush_queue<W>(a, di, n_q, q_ent, q_val, q_pos, mine, tile_keys, tile_psi, acc);
-                n_q = 0;
-                mine = 0;
+            const uint32_t m0 = mh[0], m1 = mh[1];
+            // this lane's row l = 32g + l%32 is in its product g (its 16 columns) and in
+            // product g of lane l^32 (the other 16): each lane keeps one mask, sends the other
+            uint32_t M = (g ? m1 : m0) | (uint32_t)__shfl_xor((int)(g ? m0 : m1), 32);
+            M &= cnt - t0 >= 32 ? 0xffffffffu : ((1u << (cnt - t0)) - 1u);  // columns inside the tile
+            if (!active) M = 0u;
+            // the group's entries in row order, each row's in column order: row lane l
+            // owns entries [excl, incl) of the group
+            const int cr = __popc(M);
+            int incl = cr;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const int excl = incl - cr;
+            const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+            for (int done = 0; done < total;) {
+                // entries [done, done + take) of the group fit the queue now
+                const int take = min(kQueue - n_q, total - done);
+                const int s0 = max(excl, done), s1 = min(incl, done + take);
+                if (s1 > s0) {
+                    uint32_t mm = M;
+                    for (int e = excl; e < s1; ++e) {
+                        const int bit = __builtin_ctz(mm);
+                        mm &= mm - 1u;
+                        if (e >= s0) q_ent[n_q + e - done] = ((uint32_t)lane << 16) | (uint32_t)(t0 + bit);
+                    }
+                    q_seg[lane * kSlots + mine++] = (uint16_t)((n_q + s0 - done) | ((s1 - s0) << 8));
+                }
+                n_q += take;
+                done += take;
+                if (done < total || n_q >= kWave || __ballot(mine >= kSlots) != 0ull) {
+                    __builtin_amdgcn_wave_barrier();
+                    flush_queue<W>(a, di, n_q, q_ent, q_val, q_seg, mine, tile_keys, tile_psi, acc);
+                    n_q = 0;
+                    mine = 0;
+                    build_rows();
+                }
             }
         }
         if (n_q > 0) {
             __builtin_amdgcn_wave_barrier();
-            flush_queue<W>(a, di, n_q, q_ent, q_val, q_pos, mine, tile_keys, tile_psi, acc);
+            flush_queue<W>(a, di, n_q, q_ent, q_val, q_seg, mine, tile_keys, tile_psi, acc);
         }
     }
     if (active) a.partial_rows[(int64_t)cb * a.n_sel + i] = acc;
