@@ -1930,8 +1930,14 @@ template <int W>
 static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_in, const int64_t *n_set_in,
                           uint64_t *set_out, int64_t *n_set_out, int64_t set_cap, uint64_t *novel,
                           int64_t *n_novel, int64_t novel_cap, char *ws, uint32_t *flags, hipStream_t st,
-                          bool check_set, bool cand_scratch) {
+                          bool check_set, bool cand_scratch, hipEvent_t after_split) {
     using C = DCfg<W>;
+    bool split_marked = false;
+    auto mark_split = [&]() -> hipError_t {
+        if (!after_split || split_marked) return hipSuccess;
+        split_marked = true;
+        return hipEventRecord(after_split, st);
+    };
     const WsLayout L = ws_layout<W>(n, cand_scratch);
     uint64_t *bufA = (uint64_t *)(ws + L.bufA);
     // the second level writes over the candidates when they may be overwritten
@@ -1960,6 +1966,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             SCI_HIP_TRY(launch_set_i64(n_set_out, 0, st));
             if (n_novel) SCI_HIP_TRY(launch_set_i64(n_novel, 0, st));
         }
+        SCI_HIP_TRY(mark_split());
         return SCI_OK;
     }
 
@@ -2028,6 +2035,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
             } else {
                 SCI_LAUNCH(splitter_kernel<W>, dim3(S_cur), dim3(kDThreads), 0, st, a);
             }
+            if (lvl == 0) SCI_HIP_TRY(mark_split());
             SCI_LAUNCH(plan_kernel, dim3(1), dim3(kDThreads), 0, st, a);
             if (lvl == 0) {
                 SCI_LAUNCH((hist_kernel<W, C::F1>), dim3((unsigned)tiles_bound), dim3(kHThreads), 0, st, a);
@@ -2103,6 +2111,7 @@ static int32_t dedup_impl(const uint64_t *cand, int64_t n, const uint64_t *set_i
     SCI_LAUNCH(finish_counts_kernel, dim3(1), dim3(64), 0, st, (const int64_t *)(scal + 0),
                (const int64_t *)(scal + 1), n_set_out, set_cap, n_novel, novel_cap, novel ? 1 : 0, flags);
     SCI_HIP_TRY(hipGetLastError());
+    SCI_HIP_TRY(mark_split());
     return SCI_OK;
 }
 
@@ -2136,7 +2145,7 @@ int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_can
                             const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
                             uint64_t *novel, int64_t *n_novel, int64_t novel_capacity, void *workspace,
                             size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in,
-                            bool cand_scratch) {
+                            bool cand_scratch, hipEvent_t after_split) {
     set_error("");
     if (n_words < 1 || n_words > SCI_MAX_WORDS)
         return fail(n_words < 1 ? SCI_EINVAL : SCI_EUNSUPPORTED, "sci_dedup_merge: n_words=%d", n_words);
@@ -2155,9 +2164,10 @@ int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_can
         return fail(SCI_ECAPACITY, "sci_dedup_merge: workspace %zu < %zu bytes", workspace_bytes, need);
     if (n_words == 1)
         return dedup_impl<1>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                             novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch);
+                             novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch,
+                             after_split);
     return dedup_impl<2>(cand, n_cand, set_in, n_set_in, set_out, n_set_out, set_capacity, novel, n_novel,
-                         novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch);
+                         novel_capacity, (char *)workspace, dev_flags, st, check_set_in, cand_scratch, after_split);
 }
 
 }  // namespace sci

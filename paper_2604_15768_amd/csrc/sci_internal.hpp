@@ -247,12 +247,14 @@ hipError_t device_scan(int64_t *x, const int64_t *n_dev, int64_t n_bound, int64_
 int64_t device_scan_sums(int64_t n_bound);
 
 // sci_dedup_merge, with the strict-order check of set_in optional; with cand_scratch
-// the candidate buffer is overwritten (the caller owns it)
+// the candidate buffer is overwritten (the caller owns it); after_split, when given,
+// is recorded on st once the first partition level's splitters are chosen (or, on
+// paths without them, before the call returns)
 int32_t dedup_merge_checked(int32_t n_words, const uint64_t *cand, int64_t n_cand, const uint64_t *set_in,
                             const int64_t *n_set_in, uint64_t *set_out, int64_t *n_set_out, int64_t set_capacity,
                             uint64_t *novel, int64_t *n_novel, int64_t novel_capacity, void *workspace,
                             size_t workspace_bytes, uint32_t *dev_flags, hipStream_t st, bool check_set_in,
-                            bool cand_scratch = false);
+                            bool cand_scratch = false, hipEvent_t after_split = nullptr);
 size_t dedup_ws_bytes(int32_t n_words, int64_t n_cand, bool cand_scratch);
 __host__ __device__ inline int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

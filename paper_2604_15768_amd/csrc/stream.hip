@@ -41,12 +41,13 @@ static StreamLayout stream_layout(int W, int64_t chunk) {
 // events of one call, released on every return path (destroying an event with
 // work still pending on it is allowed; the release happens when it completes)
 struct StreamEvents {
-    hipEvent_t ready[2] = {nullptr, nullptr}, filled[2] = {nullptr, nullptr};
+    hipEvent_t ready[2] = {nullptr, nullptr}, filled[2] = {nullptr, nullptr}, split = nullptr;
     ~StreamEvents() {
         for (int b = 0; b < 2; ++b) {
             if (ready[b]) (void)hipEventDestroy(ready[b]);
             if (filled[b]) (void)hipEventDestroy(filled[b]);
         }
+        if (split) (void)hipEventDestroy(split);
     }
 };
 
@@ -97,6 +98,7 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         SCI_HIP_TRY(hipEventCreateWithFlags(&ready[b], hipEventDisableTiming));
         SCI_HIP_TRY(hipEventCreateWithFlags(&filled[b], hipEventDisableTiming));
     }
+    SCI_HIP_TRY(hipEventCreateWithFlags(&ev.split, hipEventDisableTiming));
 
     const uint64_t *cur_set = set_in;
     const int64_t *cur_n = set_in ? n_set_in : nullptr;
@@ -117,6 +119,10 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         const int64_t e0 = exc_begin + k * chunk;
         const int64_t e1 = e0 + chunk < exc_end ? e0 + chunk : exc_end;
         if (k >= 2) SCI_HIP_TRY(hipStreamWaitEvent(sg, ready[b], 0));  // buffer b free again
+        // the next chunk is generated once the previous chunk's dedup has chosen its first
+        // splitters: its small, latency-bound sample sort then does not queue behind
+        // a full-chip generation launch, which overlaps the partition passes instead
+        if (k >= 1) SCI_HIP_TRY(hipStreamWaitEvent(sg, ev.split, 0));
         st = sci_gen_coupled(ham, dets, n_dets, e0, e1, -1.0, (uint64_t *)(ws + L.keys[b]), (double *)(ws + L.hij[b]),
                              nullptr, chunk, (int64_t *)(ws + L.n_gen), dev_flags, gen_stream);
         if (st != SCI_OK) break;
@@ -127,7 +133,7 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
         // caller's set_in needs the order check
         st = dedup_merge_checked(W, (const uint64_t *)(ws + L.keys[b]), e1 - e0, cur_set, cur_n, dst, n_set_out,
                                  set_capacity, nullptr, nullptr, 0, ws + L.dedup, workspace_bytes - L.dedup,
-                                 dev_flags, sd, /*check_set_in=*/k == 0, /*cand_scratch=*/true);
+                                 dev_flags, sd, /*check_set_in=*/k == 0, /*cand_scratch=*/true, ev.split);
         if (st != SCI_OK) break;
         SCI_HIP_TRY(hipEventRecord(ready[b], sd));
         int64_t *n_run = (int64_t *)(ws + L.n_run);
