@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--large-sources", type=int, default=32768)
     ap.add_argument("--large-chunk", type=int, default=1 << 31,
                     help="pool chunk in candidates (0: time 2^29, 2^30, 2^31 once each and keep the fastest)")
+    ap.add_argument("--energy-after", action="store_true",
+                    help="run E and dE/dpsi after the stream of chunks instead of beside it")
     ap.add_argument("--batch-chunks", type=int, default=32,
                     help="chunks of the batched workload (each one batch over all systems)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_OUTPUT"),
@@ -474,13 +476,25 @@ def large_headline(args, torch, sci, si, copy_gbps):
     if sizes is not None and cap < sizes[-1]["m1"]:
         raise SystemExit(f"set buffers of {cap} keys cannot hold the union of {sizes[-1]['m1']}")
 
+    # E and dE/dpsi over S read only S and psi, not the union the stream builds: by
+    # default they run on a stream of their own beside the stream of chunks (the step
+    # ends when both have); the step's stages are the stream of chunks, then the rest
+    # of the energy that did not fit beside it
+    es = torch.cuda.Stream()
+
     def step(ev):
         ev[0].record(cur)
+        if not args.energy_after:
+            es.wait_stream(cur)
+            sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, es)
         sci.sci_stream_dedup(ham, dets, n_src, 0, total, chunk, sel, n_in, set_a, set_b, cap, n_out,
                              ws, ws.numel(), flags, cur, dd)
         cur.wait_stream(dd)
         ev[1].record(cur)
-        sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, cur)
+        if args.energy_after:
+            sci.sci_energy(ham, sel, n_sel, psi, energy, hpsi, grad, ws_e, ws_e.numel(), flags, cur)
+        else:
+            cur.wait_stream(es)
         ev[2].record(cur)
 
     warm = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -508,7 +522,9 @@ def large_headline(args, torch, sci, si, copy_gbps):
                         f"device pool in chunks of {chunk} into S (sci_stream_dedup) + E and dE/dpsi over S",
             "n_candidates": total, "n_unique_union": n_union, "chunk": chunk,
             "n_chunks": -(-total // chunk),
-            "stage_ms": {"gen_dedup_stream": s_ms, "energy_grad": stages["energy"]},
+            "stage_ms": {"gen_dedup_stream": s_ms,
+                         ("energy_grad" if args.energy_after else "energy_grad_after_stream"): stages["energy"]},
+            "energy_placement": "after the stream" if args.energy_after else "beside the stream (own stream)",
             "candidates_per_s_stream": total / (s_ms / 1000.0),
             "energy": float(energy.item()),
             "device_bytes": {"pool_and_workspace": ws.numel(), "set_buffers": 2 * cap * kb, "peak_allocated": peak},
