@@ -399,6 +399,35 @@ def test_energy_tiny_matches_oracle(method):
 
 
 @pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("n,na,nb,n_sel", [
+    (5, 1, 0, None),     # one electron: the screening bias 2 - N is positive
+    (6, 1, 1, None),     # two electrons: every pair of the space is connected
+    (7, 2, 1, None),     # three electrons
+    (16, 2, 2, None),    # 2n = 32 spin orbitals: one 32-bit chunk
+    (17, 3, 2, 3000),    # 2n = 34: a second, mostly empty chunk
+    (33, 2, 2, 4000),    # two words, 2n = 66: three chunks
+    (64, 2, 3, 3000),    # two words, 2n = 128: four full chunks
+])
+def test_energy_shapes_match_oracle(n, na, nb, n_sel, method):
+    """E, H psi and the gradient against the oracle on spaces that exercise the edges of
+    the pair screening: electron counts of 1-3, spin-orbital counts that fill one, part
+    of two, three or four 32-bit chunks, and row or column blocks left partly empty."""
+    import torch
+    sci = require_gpu()
+    sm = si.make_system(si.small_workload(n, na, nb, n_sel=n_sel, seed=300 + n + na))
+    say(f"energy shape n={n} {na}a+{nb}b n_sel={sm.dets.shape[0]} {method}")
+    h = sci.Ham(sm.n_orb, sm.n_alpha, sm.n_beta, sm.h1, sm.eri)
+    e, hp, g, flags = sci.energy(h, sci.keys_to_device(sm.dets), torch.from_numpy(sm.psi).cuda(),
+                                 method=_method(sci, method))
+    torch.cuda.synchronize()
+    assert sci.check_flags(flags, "energy") == 0
+    oe, ohp, og = oracle.energy(sm.n_orb, sm.n_alpha, sm.n_beta, sm.h1, sm.eri, sm.dets, sm.psi)
+    assert abs(e.item() - oe) <= E_TOL
+    assert np.max(np.abs(hp.cpu().numpy() - ohp)) <= H_TOL * 10
+    assert np.max(np.abs(g.cpu().numpy() - og)) <= G_TOL
+
+
+@pytest.mark.parametrize("method", METHODS)
 def test_energy_full_space_eigenvector(method):
     import torch
     sci = require_gpu()
