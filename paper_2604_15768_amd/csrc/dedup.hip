@@ -1147,8 +1147,10 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
     }
 }
 
-// Three workgroups per CU: LDS holds 2 x 24 KB of keys for each (3,072 one-word or
-// 1,536 two-word keys), and at most 80 VGPRs leave room for their 24 waves.
+// LDS holds 24 KB of keys per workgroup (3,072 one-word or 1,536 two-word keys) and a
+// hash table of 16-bit slots (16 / 8 KB): four workgroups per CU for two-word keys,
+// three for one-word keys.  The radix passes sort in place: each pass holds its keys in
+// registers from before its first barrier, so it writes back into the buffer it read.
 //
 // The running set's keys of the unit's range are looked up in the unit's hash table
 // before anything is sorted: a short range is streamed through the table (its first
@@ -1162,8 +1164,10 @@ void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
     constexpr int kSP = 2;                                      // set keys per thread loaded up front
-    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's novel keys
-    __shared__ Key<W> s_k1[C::CAP];          // hash table while hashing; radix ping-pong after
+    // table slots: the smallest power of two at least twice the capacity (load at most 1/2)
+    constexpr int kLogTab = 32 - __builtin_clz(2u * C::CAP - 1u);
+    __shared__ Key<W> s_k0[C::CAP];          // candidate keys, then each wave's novel keys, sorted in place
+    __shared__ uint32_t s_tab[(1 << kLogTab) / 2];  // hash table, two 16-bit slots per word
     __shared__ __align__(8) uint16_t s_cnt[kBWaves][256];  // per-wave digit counts, then output offsets
     __shared__ uint32_t s_dup[C::CAP / 32];  // bit i: the key at position i is a set key
     __shared__ uint64_t s_or[2];
@@ -1218,7 +1222,7 @@ void bucket_kernel(BucketArgs a) {
         int log_t = 4;
         while ((1 << log_t) < 2 * m) ++log_t;
         const uint32_t tmask = (1u << log_t) - 1u;
-        uint32_t *tab = reinterpret_cast<uint32_t *>(s_k1);
+        uint32_t *tab = s_tab;
         for (int i = threadIdx.x; i < (1 << log_t) / 2; i += kBThreads) tab[i] = 0xffffffffu;
         for (int i = threadIdx.x; i < C::CAP / 32; i += kBThreads) s_dup[i] = 0u;
         if (threadIdx.x == 0) s_or[0] = s_or[1] = 0;
@@ -1331,10 +1335,9 @@ void bucket_kernel(BucketArgs a) {
 #pragma unroll
         for (int ww = 0; ww < kBWaves; ++ww) u += s_u[ww];
 
-        // stable LSD radix sort of the u novel keys, LDS resident.  The first pass
+        // stable LSD radix sort of the u novel keys, in place in LDS.  The first pass
         // reads every wave's own slice (any starting order is fine); later passes
         // read the contiguous result of the previous pass.
-        Key<W> *cur = s_k0, *nxt = s_k1;
         const int Kd = (u + kBThreads - 1) / kBThreads;
         const int CHd = Kd * kWave;
         bool first = true;
@@ -1346,10 +1349,7 @@ void bucket_kernel(BucketArgs a) {
             const int base_pos = first ? my0 : w * CHd;
             const int rounds = first ? (uw + kWave - 1) / kWave : Kd;  // the first pass reads only this wave's keys
             const int limit = first ? my0 + uw : u;
-            unit_radix_pass<W, kBK>(cur, nxt, shift, vm, base_pos, rounds, limit, s_cnt);
-            Key<W> *t = cur;
-            cur = nxt;
-            nxt = t;
+            unit_radix_pass<W, kBK>(s_k0, s_k0, shift, vm, base_pos, rounds, limit, s_cnt);
             first = false;
         }
         if (first) {
@@ -1357,14 +1357,13 @@ void bucket_kernel(BucketArgs a) {
             if (threadIdx.x == 0) {
                 for (int ww = 0; ww < kBWaves; ++ww)
                     if (s_u[ww] > 0) {
-                        s_k1[0] = s_k0[ww * CHm];
+                        s_k0[0] = s_k0[ww * CHm];
                         break;
                     }
             }
             __syncthreads();
-            cur = s_k1;
         }
-        for (int i = threadIdx.x; i < u; i += kBThreads) store_key<W>(a.dst, start + i, cur[i]);
+        for (int i = threadIdx.x; i < u; i += kBThreads) store_key<W>(a.dst, start + i, s_k0[i]);
         if (threadIdx.x == 0) {
             a.nuniq[s] = u;
             a.ucount[s] = u + nb;
