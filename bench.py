@@ -66,8 +66,9 @@ def parse():
     ap.add_argument("--extras", default="whole,medium,select,screened,energy,batch",
                     help="comma list of extras (whole, medium, select, screened, energy, batch)")
     ap.add_argument("--large-sources", type=int, default=32768)
-    ap.add_argument("--large-chunk", type=int, default=1 << 31,
-                    help="pool chunk in candidates (0: time 2^29, 2^30, 2^31 once each and keep the fastest)")
+    ap.add_argument("--large-chunk", type=int, default=-1,
+                    help="pool chunk in candidates (-1: the fewest equal chunks of at most LARGE_CHUNK_MAX; "
+                         "0: time 2^29, 2^30, 2^31 and the default once each and keep the fastest)")
     ap.add_argument("--energy-after", action="store_true",
                     help="run E and dE/dpsi after the stream of chunks instead of beside it")
     ap.add_argument("--batch-chunks", type=int, default=32,
@@ -120,6 +121,11 @@ def _template_args(name, fam):
         k += 1
     return [a.strip() for a in name[j:k - 1].split(",")]
 
+
+# largest pool chunk of the large-workload mini-batch (candidates): with two pool buffers
+# of (key + H_ij) and the dedup workspace it leaves about 140 GB of HBM for the set
+# buffers, which hold the 3.06e9-key union of the mini-batch twice with room to spare
+LARGE_CHUNK_MAX = 2_400_000_000
 
 # fan-outs of the two partition levels as the compiled kernels spell them (DCfg<W>)
 FANOUT = {1: {"C::F1": "4096", "C::F2": "512"}, 2: {"C::F1": "4096", "C::F2": "1024"}}
@@ -454,10 +460,15 @@ def large_headline(args, torch, sci, si, copy_gbps):
     ws_e = torch.empty(sci.sci_energy_workspace_bytes(n_sel), dtype=torch.uint8, device=dev)
     flags = sci.new_flags(dev)
 
-    chunk = args.large_chunk
-    if chunk <= 0:  # sweep: one timed pass each after a warm-up pass
+    # Every chunk merges into the whole running set, so fewer chunks read and rewrite it
+    # fewer times; equal chunks of at most LARGE_CHUNK_MAX candidates leave room for the
+    # set buffers of the union beside the two pool buffers and the dedup workspace
+    n_eq = -(-total // LARGE_CHUNK_MAX)
+    equal_chunk = -(-total // n_eq)
+    chunk = args.large_chunk if args.large_chunk > 0 else equal_chunk
+    if args.large_chunk == 0:  # sweep: one timed pass each after a warm-up pass
         sweep = {}
-        for c in (1 << 29, 1 << 30, 1 << 31):
+        for c in (1 << 29, 1 << 30, 1 << 31, equal_chunk):
             ws, set_a, set_b, cap = buffers(c)
             run = lambda: (sci.sci_stream_dedup(ham, dets, n_src, 0, total, c, sel, n_in, set_a, set_b, cap, n_out,
                                                 ws, ws.numel(), flags, cur, dd), cur.wait_stream(dd))

@@ -2,7 +2,8 @@
 
 Medium workload: the whole step's generation (2.51e9 candidates) and its dedup-merge
 into S.  Large workload: one 32,768-source mini-batch (1.18e10 candidates) streamed
-in pool chunks of 2^31 into S.  The oracle computes sampled sources one by one.
+in the pool chunks the benchmark streams (five equal chunks of 2,367,488,000) into S.  The
+oracle computes sampled sources one by one.
 Every key of each union is checked: the key space is cut into ranges at union keys,
 and in each range the union must equal a library sort + unique of every candidate
 (and selected key) that falls in it (the large mini-batch's candidates are
@@ -151,10 +152,12 @@ def test_large_streamed_minibatch_exact_ranges():
     h = ham("large")
     assert h.W == 2
     _free()
-    n_src, chunk = 32768, 1 << 31  # the pool chunk the benchmark streams
+    n_src = 32768
     sel = sci.keys_to_device(s.dets)
     dets = sel[:n_src]
     total = n_src * h.n_coupled
+    # the pool chunk the benchmark streams: the fewest equal chunks of at most 2.4e9
+    chunk = -(-total // -(-total // 2_400_000_000))
     cap = 3_300_000_000
     say(f"large mini-batch: {total} candidates, chunks of {chunk}, set capacity {cap}")
     union, n_union, flags = sci.stream_dedup(h, dets, chunk, sel, cap, dedup_stream=torch.cuda.Stream())
