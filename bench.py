@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=0,
-                    help="sources of the oracle sample (0: 192 large, 8000 medium, all tiny)")
+                    help="sources of the oracle sample (0: 480 large, 8000 medium, all tiny)")
     ap.add_argument("--cpu-single-sources", type=int, default=-1,
                     help="sources of the single-thread oracle sample (0: skip; -1: per workload)")
     ap.add_argument("--medium-cpu-sources", type=int, default=25000,
@@ -926,7 +926,7 @@ def batch_extras(args, torch, sci, si):
 # CPU baseline: the oracle as it stands on a bounded sample
 # ---------------------------------------------------------------------------
 
-DEFAULT_CPU_SOURCES = {"large": 192, "medium": 8000, "tiny": 200}
+DEFAULT_CPU_SOURCES = {"large": 480, "medium": 8000, "tiny": 200}
 DEFAULT_SINGLE_SOURCES = {"large": 16, "medium": 500, "tiny": 200}
 
 

@@ -312,7 +312,10 @@ int32_t sci_energy_noalloc(sci_ham_t ham, const uint64_t *sel, int64_t n_sel, co
  * sci_gen_coupled) is cut into chunks of at most `chunk` candidates.  Chunk k
  * is generated (dense mode) into pool buffer k%2 on `gen_stream`; the keys are
  * de-duplicated and merged into the running set on `dedup_stream`, while chunk
- * k+1 is generated into the other buffer.  The running set starts as set_in
+ * k+1 is generated into the other buffer (its generation starts once the dedup
+ * of chunk k has chosen its first-level splitters and the dedup of chunk k-1
+ * has released the buffer).  `chunk` is below 2^32 (one sci_dedup_merge call
+ * per chunk; SCI_EUNSUPPORTED otherwise).  The running set starts as set_in
  * (strictly ascending, device count n_set_in) and alternates between set_a and
  * set_b (each set_capacity keys); *final_is_b (host) tells which one holds the
  * result, *n_set_out (device int64) its size.  H_ij values are produced into

@@ -78,6 +78,9 @@ extern "C" int32_t sci_stream_dedup(sci_ham_t ham, const uint64_t *dets, int64_t
     if (!ham) return fail(SCI_EINVAL, "sci_stream_dedup: NULL handle");
     const int W = ham->dev.W;
     if (chunk < 1) return fail(SCI_EINVAL, "sci_stream_dedup: chunk must be >= 1");
+    if (chunk >= (1ll << 32))
+        return fail(SCI_EUNSUPPORTED, "sci_stream_dedup: chunk %lld exceeds one dedup call (2^32 - 1)",
+                    (long long)chunk);
     if (!set_a || !set_b || set_a == set_b || !n_set_out || !final_is_b || !workspace || !dev_flags)
         return fail(SCI_EINVAL, "sci_stream_dedup: NULL or aliased argument");
     if (set_in && !n_set_in) return fail(SCI_EINVAL, "sci_stream_dedup: set_in without n_set_in");

@@ -591,6 +591,24 @@ def test_stream_dedup_matches_oracle(name, n_src, chunk):
     assert np.array_equal(sci.keys_to_host(out2[:int(n2.item())]), ou2)
 
 
+def test_stream_dedup_rejects_chunks_above_one_dedup_call():
+    """A chunk of 2^32 candidates or more is refused before anything is enqueued."""
+    import ctypes
+    import torch
+    sci = require_gpu()
+    h = ham("tiny")
+    s = system("tiny")
+    sel = sci.keys_to_device(s.dets)
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    P = ctypes.c_void_p
+    fin = ctypes.c_int32(0)
+    rc = sci._lib.sci_stream_dedup(h._h, P(sel.data_ptr()), sel.shape[0], 0, 10, 1 << 32, P(sel.data_ptr()),
+                                   P(d.data_ptr()), P(d.data_ptr()), P(d.data_ptr() + 8), 1, P(d.data_ptr()),
+                                   ctypes.byref(fin), P(d.data_ptr()), 8, P(d.data_ptr()), None, None)
+    assert rc == sci.SCI_EUNSUPPORTED
+    assert "exceeds one dedup call" in sci._lib.sci_last_error().decode()
+
+
 def test_stream_dedup_overflow_truncates_running_set():
     """When the running set overflows its capacity mid-stream, later chunks merge into the
     kept (first set_capacity) keys only.  Expected values follow that rule with the oracle:
