@@ -732,9 +732,9 @@ def whole_extras(args, torch, sci, ham, sel):
     W = ham.W
     n_sel = sel.shape[0]
     total = n_sel * ham.n_coupled
-    # chunks of 2^30: set buffers for the 5.5e9-key union (179 GB) leave no room for a
-    # 2^31 pool beside them
-    chunk = 1 << 30
+    # the fewest equal chunks of at most 1.6e9 candidates: set buffers for the 5.5e9-key
+    # union take 179 GB, the pool and dedup workspace of such a chunk about 105 GB
+    chunk = -(-total // -(-total // 1_600_000_000))
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats(dev)
     ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)
@@ -742,7 +742,7 @@ def whole_extras(args, torch, sci, ham, sel):
     free_bytes = torch.cuda.mem_get_info(dev)[0]
     # the union lies in the determinants of excitation level <= 4 of the reference
     # (5.55e9 for this system), so larger set buffers would stay unused
-    cap = int(min(total + n_sel, 5_600_000_000, (free_bytes - (16 << 30)) // (2 * W * 8)))
+    cap = int(min(total + n_sel, 5_600_000_000, (free_bytes - (8 << 30)) // (2 * W * 8)))
     set_a = torch.empty((cap, W), dtype=torch.int64, device=dev)
     set_b = torch.empty_like(set_a)
     n_in = torch.tensor([n_sel], dtype=torch.int64, device=dev)
