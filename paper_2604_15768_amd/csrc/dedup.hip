@@ -1527,17 +1527,37 @@ __global__ __launch_bounds__(kBThreads) void bucket_stream_kernel(BucketArgs a) 
 // grid-stride order from the device list.
 template <int W>
 __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
+    using C = DCfg<W>;
     __shared__ BucketLds L;
+    // a unit of up to SCAP keys (the splitter kernel's LDS sort) is sorted in LDS, a
+    // larger one over global memory
+    __shared__ Key<W> s_buf[C::SCAP];
+    __shared__ Key<W> s_tmp[C::SCAP];
     const int64_t n_big = *a.n_big2;
     for (int64_t t = blockIdx.x; t < n_big; t += gridDim.x) {
         const int64_t s = a.big2[t];
         int64_t start, size;
         unit_span(a, s, start, size);
         const int64_t bl = a.bstart[s], bh = bl + a.bcount[s];
-        uint64_t *X = const_cast<uint64_t *>(a.src) + start * W;
-        uint64_t *Y = a.dst + start * W;
-        const int where = global_radix_sort<W>(X, X, Y, size, L.R, L.gbase, L.dtot);
-        const uint64_t *res = where ? Y : X;
+        const bool in_lds = size <= C::SCAP;
+        const uint64_t *res = nullptr;
+        const Key<W> *lres = nullptr;
+        if (in_lds) {
+            const int m = (int)size;
+            for (int i = threadIdx.x; i < m; i += kDThreads) s_buf[i] = load_key<W>(a.src, start + i);
+            __syncthreads();
+            const Key<W> ref = s_buf[0];
+            __syncthreads();
+            Key<W> orkey;
+            const int nbits = block_varying_bits<W>(m, ref, [&](int64_t i) { return s_buf[i]; }, L.R, &orkey);
+            lres = lds_radix_sort<W, C::SCAP>(s_buf, s_tmp, m, nbits, orkey, L.R);
+        } else {
+            uint64_t *X = const_cast<uint64_t *>(a.src) + start * W;
+            uint64_t *Y = a.dst + start * W;
+            const int where = global_radix_sort<W>(X, X, Y, size, L.R, L.gbase, L.dtot);
+            res = where ? Y : X;
+        }
+        auto key_at = [&](int64_t i) { return in_lds ? lres[i] : load_key<W>(res, i); };
         // first occurrences the running set does not hold, compacted in order
         int64_t run = 0;
         for (int64_t i0 = 0; i0 < size; i0 += kDThreads) {
@@ -1545,8 +1565,8 @@ __global__ __launch_bounds__(kDThreads) void bucket_big_kernel(BucketArgs a) {
             Key<W> cur;
             bool keep = false;
             if (i < size) {
-                cur = load_key<W>(res, i);
-                keep = (i == 0) || !key_eq<W>(cur, load_key<W>(res, i - 1));
+                cur = key_at(i);
+                keep = (i == 0) || !key_eq<W>(cur, key_at(i - 1));
             }
             __syncthreads();  // every read of this round precedes the writes (in place when res == dst)
             if (keep && bh > bl && contains_set<W>(a.B, bl, bh, cur)) keep = false;
