@@ -589,11 +589,27 @@ __global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
     // (i+1) >> (ctz(i+1)+1) in that level.  The lanes of a wave then read one
     // contiguous level per step instead of entries a power of two apart (which fall
     // into the same LDS bank), and every search takes exactly log2(FMAX) steps.
+    // Two-word keys: when every splitter of the segment has the same top word X (most
+    // level-2 segments: a level-1 bucket inside one top word), the tree holds only the
+    // low words, half the LDS reads per step; keys with another top word have every
+    // splitter above them (top word below X) or below them (above X).
+    bool one_top = false;
+    uint64_t X = 0;
+    if constexpr (W == 2) {
+        if (f > 2) {
+            X = sp[1];
+            one_top = sp[(int64_t)(f - 2) * W + 1] == X;
+        }
+    }
+    uint64_t *s_low = reinterpret_cast<uint64_t *>(s_spl);  // [FMAX - 1] when one_top
     for (int i = threadIdx.x; i < FMAX - 1; i += kH) {
         const int z = __builtin_ctz((unsigned)(i + 1));
         const int j = (1 << (kSteps - 1 - z)) + ((i + 1) >> (z + 1));
-        if (i < f - 1) s_spl[j - 1] = load_key<W>(sp, i);
-        else {
+        if (one_top) {
+            s_low[j - 1] = i < f - 1 ? sp[(int64_t)i * W] : ~0ull;
+        } else if (i < f - 1) {
+            s_spl[j - 1] = load_key<W>(sp, i);
+        } else {
 #pragma unroll
             for (int q = 0; q < W; ++q) s_spl[j - 1].w[q] = ~0ull;
         }
@@ -619,13 +635,26 @@ __global__ __launch_bounds__(kHThreads) void hist_kernel(LevelArgs a) {
         // so the leaf reached, less FMAX, is the number of splitters below the key
 #pragma unroll
         for (int u = 0; u < 4; ++u) pos[u] = 1;
+        if (one_top) {  // workgroup-uniform
 #pragma unroll
-        for (int st = 0; st < kSteps; ++st) {
+            for (int st = 0; st < kSteps; ++st) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pos[u] = 2 * pos[u] + (key_less<W>(s_spl[pos[u] - 1], k[u]) ? 1 : 0);
+                for (int u = 0; u < 4; ++u) pos[u] = 2 * pos[u] + (s_low[pos[u] - 1] < k[u].w[0] ? 1 : 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                pos[u] -= FMAX;
+                if (k[u].w[W - 1] != X) pos[u] = k[u].w[W - 1] < X ? 0 : f - 1;
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < kSteps; ++st) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pos[u] = 2 * pos[u] + (key_less<W>(s_spl[pos[u] - 1], k[u]) ? 1 : 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pos[u] -= FMAX;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pos[u] -= FMAX;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t i = i0 + u * kH + threadIdx.x;
