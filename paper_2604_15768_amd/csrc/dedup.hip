@@ -1368,6 +1368,60 @@ void bucket_kernel(BucketArgs a) {
         // reads every wave's own slice (any starting order is fine); later passes
         // read the contiguous result of the previous pass.
         const int Kd = (u + kBThreads - 1) / kBThreads;
+        const int CHd0 = Kd * kWave;
+        if constexpr (W == 2) {
+            if (orx[1] == 0ull) {  // workgroup-uniform
+                // Every novel key has the top word of `ref` (most units lie in one top
+                // word): the low words are sorted alone, half the LDS bytes per pass, and
+                // the top word is put back as the run is written.  Each wave's keys move
+                // to the same positions of an 8-byte view, read before any is written.
+                Key<1> *s_lw = reinterpret_cast<Key<1> *>(s_k0);
+                uint64_t lw[kBK];
+#pragma unroll
+                for (int k = 0; k < kBK; ++k)
+                    if (k * kWave + lane < uw) lw[k] = s_k0[my0 + k * kWave + lane].w[0];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kBK; ++k)
+                    if (k * kWave + lane < uw) s_lw[my0 + k * kWave + lane].w[0] = lw[k];
+                __syncthreads();
+                Key<1> orlow;
+                orlow.w[0] = orx[0];
+                bool first1 = true;
+                for (int shift = lo_bit; shift < nbits; shift += 8) {
+                    const uint32_t vm = digit_of<1>(orlow, shift);
+                    if (vm == 0u) continue;  // workgroup-uniform
+                    const int base_pos = first1 ? my0 : w * CHd0;
+                    const int rounds = first1 ? (uw + kWave - 1) / kWave : Kd;
+                    const int limit = first1 ? my0 + uw : u;
+                    unit_radix_pass<1, kBK>(s_lw, s_lw, shift, vm, base_pos, rounds, limit, s_cnt);
+                    first1 = false;
+                }
+                if (first1) {
+                    // no pass ran: at most one novel key
+                    if (threadIdx.x == 0) {
+                        for (int ww = 0; ww < kBWaves; ++ww)
+                            if (s_u[ww] > 0) {
+                                s_lw[0] = s_lw[ww * CHm];
+                                break;
+                            }
+                    }
+                    __syncthreads();
+                }
+                for (int i = threadIdx.x; i < u; i += kBThreads) {
+                    Key<W> k;
+                    k.w[0] = s_lw[i].w[0];
+                    k.w[1] = ref.w[1];
+                    store_key<W>(a.dst, start + i, k);
+                }
+                if (threadIdx.x == 0) {
+                    a.nuniq[s] = u;
+                    a.ucount[s] = u + nb;
+                    a.ncount[s] = u;
+                }
+                return;
+            }
+        }
         const int CHd = Kd * kWave;
         bool first = true;
         // digits cover only the bits that vary among the novel keys; a window in which
