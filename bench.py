@@ -122,10 +122,20 @@ def _template_args(name, fam):
     return [a.strip() for a in name[j:k - 1].split(",")]
 
 
+def equal_chunks(total, max_chunk):
+    """The fewest equal pool chunks of at most max_chunk candidates: (chunk, count)."""
+    n = -(-total // max_chunk)
+    chunk = -(-total // n)
+    return chunk, -(-total // chunk)
+
+
 # largest pool chunk of the large-workload mini-batch (candidates): with two pool buffers
 # of (key + H_ij) and the dedup workspace it leaves about 140 GB of HBM for the set
 # buffers, which hold the 3.06e9-key union of the mini-batch twice with room to spare
 LARGE_CHUNK_MAX = 2_400_000_000
+# the same for all of S streamed into one set, whose 5.5e9-key union needs 179 GB of
+# set buffers
+WHOLE_CHUNK_MAX = 1_600_000_000
 
 # fan-outs of the two partition levels as the compiled kernels spell them (DCfg<W>)
 FANOUT = {1: {"C::F1": "4096", "C::F2": "512"}, 2: {"C::F1": "4096", "C::F2": "1024"}}
@@ -463,8 +473,7 @@ def large_headline(args, torch, sci, si, copy_gbps):
     # Every chunk merges into the whole running set, so fewer chunks read and rewrite it
     # fewer times; equal chunks of at most LARGE_CHUNK_MAX candidates leave room for the
     # set buffers of the union beside the two pool buffers and the dedup workspace
-    n_eq = -(-total // LARGE_CHUNK_MAX)
-    equal_chunk = -(-total // n_eq)
+    equal_chunk, _ = equal_chunks(total, LARGE_CHUNK_MAX)
     chunk = args.large_chunk if args.large_chunk > 0 else equal_chunk
     if args.large_chunk == 0:  # sweep: one timed pass each after a warm-up pass
         sweep = {}
@@ -734,7 +743,7 @@ def whole_extras(args, torch, sci, ham, sel):
     total = n_sel * ham.n_coupled
     # the fewest equal chunks of at most 1.6e9 candidates: set buffers for the 5.5e9-key
     # union take 179 GB, the pool and dedup workspace of such a chunk about 105 GB
-    chunk = -(-total // -(-total // 1_600_000_000))
+    chunk, _ = equal_chunks(total, WHOLE_CHUNK_MAX)
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats(dev)
     ws_bytes = sci.sci_stream_workspace_bytes(ham, chunk)

@@ -104,3 +104,17 @@ def test_gen_dedup_traffic_sums_per_step(bench, monkeypatch):
     monkeypatch.setattr(bench, "recorded_traffic", lambda name, W, *rest: None)
     r0 = bench.gen_dedup_traffic(per_kernel, 1, 20.0, 5000.0)
     assert r0["achieved"] is None and r0["copy_GBps"] == 5000.0 and r0["time_covered"] == 0.0
+
+
+def test_equal_chunks_of_the_large_streams(bench):
+    # the large mini-batch: 32,768 sources x 361,250 candidates in five equal chunks
+    total = 32768 * 361250
+    chunk, n = bench.equal_chunks(total, bench.LARGE_CHUNK_MAX)
+    assert (chunk, n) == (2_367_488_000, 5) and chunk * n == total
+    # all 200,000 selected determinants as sources
+    whole = 200000 * 361250
+    chunk, n = bench.equal_chunks(whole, bench.WHOLE_CHUNK_MAX)
+    assert n == 46 and chunk <= bench.WHOLE_CHUNK_MAX and (n - 1) * chunk < whole <= n * chunk
+    # exact multiples and a single chunk
+    assert bench.equal_chunks(10, 5) == (5, 2)
+    assert bench.equal_chunks(3, 5) == (3, 1)
