@@ -304,6 +304,33 @@ def test_dedup_heavy_hitter_among_dense_neighbours(W):
     _dedup_check(sci, cand, setin, W)
 
 
+@pytest.mark.parametrize("n_straggle", [2, 1000])
+def test_dedup_shared_top_word_with_stragglers(n_straggle):
+    """Two-word keys nearly all sharing one top word X, with a few keys at X-1 and X+1.
+    Two per side are almost never among a level-2 bucket's ~4,000 samples: the
+    segment's splitters then all have the top word X, its histogram searches low words
+    only and must send the stragglers to its first or last bucket.  A thousand per
+    side are sampled and split off as usual.  Units holding a straggler sort both
+    words.  Union and novel keys against the oracle, with a set that also holds keys
+    of all three top words."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(123 + n_straggle))
+    X = np.uint64(0x0123456789ABCDEF)
+    main = np.empty((2_000_000, 2), np.uint64)
+    main[:, 0] = rng.integers(0, 2**63, size=main.shape[0], dtype=np.int64).astype(np.uint64) << np.uint64(1)
+    main[:, 1] = X
+    low = main[:n_straggle].copy()
+    low[:, 1] = X - np.uint64(1)
+    high = main[n_straggle:2 * n_straggle].copy()
+    high[:, 1] = X + np.uint64(1)
+    cand = np.concatenate([main, main[::3], low, high])  # repeats as well
+    cand = cand[rng.permutation(cand.shape[0])]
+    setin = si.sort_keys(np.concatenate([main[::11], low[::2], high[1::2]]))
+    setin = setin[np.concatenate([[True], np.any(setin[1:] != setin[:-1], axis=1)])]
+    say(f"dedup shared top word: n={cand.shape[0]} set={setin.shape[0]}")
+    _dedup_check(sci, cand, setin, 2)
+
+
 @pytest.mark.parametrize("name", ["tiny", "medium"])
 def test_dedup_of_generated_candidates(name):
     """Skewed real keys: coupled sets of a selected-set slice merged into the selected set."""
