@@ -981,7 +981,7 @@ def main():
         summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import sci_inputs as si
     if args.cpu_only:

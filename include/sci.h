@@ -49,7 +49,7 @@ typedef enum {
     SCI_ECAPACITY = 2,    /* an output buffer is too small (host-visible)    */
     SCI_ENOMEM = 3,       /* the library could not allocate its own tables   */
     SCI_EHIP = 4,         /* a HIP runtime call failed                       */
-    SCI_EUNSUPPORTED = 5  /* size outside what this build supports           */
+    SCI_EUNSUPPORTED = 5  /* size outside what the library supports          */
 } sci_status;
 
 /* bits of *dev_flags */
@@ -57,7 +57,7 @@ typedef enum {
 #define SCI_FLAG_BAD_DET 0x2u  /* a determinant has wrong popcounts / bits   */
 #define SCI_FLAG_UNSORTED 0x4u /* a set that must be strictly ascending isn't */
 
-/* Largest supported sizes of this build. */
+/* Largest sizes the library supports. */
 #define SCI_MAX_WORDS 2
 #define SCI_MAX_ORB 64
 
