@@ -1099,6 +1099,65 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
     __syncthreads();
 }
 
+// a < b where an invalid key counts as larger than every valid one
+template <int W>
+__device__ __forceinline__ bool less_valid(const Key<W> &a, bool av, const Key<W> &b, bool bv) {
+    return av && (!bv || key_less<W>(a, b));
+}
+
+// Sort of at most one key per thread of a workgroup (u <= kBThreads distinct keys):
+// thread t holds key t (valid iff t < u).  Each wave sorts its 64 keys in registers
+// with a bitonic network (partners exchanged by lane shuffles, no barrier); the sorted
+// runs of 64 are then merged pairwise in buf, each key moving to its index in its own
+// run plus its rank in the partner run (keys are distinct, so ranks never tie).  The
+// sorted keys end in buf[0, u).
+template <int W>
+__device__ __forceinline__ void small_unit_sort(Key<W> key, bool valid, int u, Key<W> *buf) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            Key<W> p;
+#pragma unroll
+            for (int q = 0; q < W; ++q) p.w[q] = __shfl_xor(key.w[q], j);
+            const bool pv = __shfl_xor((int)valid, j) != 0;
+            // ascending blocks of k lanes alternate with descending ones (the last is
+            // the whole wave, ascending); the lower lane of a pair keeps the smaller
+            // key of an ascending block
+            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+            const bool take = keep_min ? less_valid<W>(p, pv, key, valid) : less_valid<W>(key, valid, p, pv);
+            if (take) {
+                key = p;
+                valid = pv;
+            }
+        }
+    }
+    int pos = threadIdx.x;  // valid keys of each wave now lead its 64 positions
+    if (valid) buf[pos] = key;
+    __syncthreads();
+    for (int L = kWave; L < u; L <<= 1) {  // workgroup-uniform
+        int np = pos;
+        if (valid) {
+            const int r = pos / L;
+            const int ps = (r ^ 1) * L;
+            int lo = ps, hi = ps + L < u ? ps + L : u;
+            if (lo > hi) lo = hi;  // no partner run
+            const int p0 = lo;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key_less<W>(buf[mid], key)) lo = mid + 1;
+                else hi = mid;
+            }
+            np = (r & ~1) * L + (pos - r * L) + (lo - p0);
+        }
+        __syncthreads();  // every search of this round has read buf
+        if (valid) buf[np] = key;
+        pos = np;
+        __syncthreads();
+    }
+}
+
 // The sorted unique run of unit s (cur[0..u) in LDS), less the keys the running set
 // already holds in the unit's range, to its place in dst, and the unit's counts:
 // the run that emit merges is then disjoint from the set keys it is merged with.
@@ -1180,6 +1239,10 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
 // hash table of 16-bit slots (16 / 8 KB): four workgroups per CU for two-word keys,
 // three for one-word keys.  The radix passes sort in place: each pass holds its keys in
 // registers from before its first barrier, so it writes back into the buffer it read.
+// A unit left with at most one novel key per thread (most units once the set holds the
+// earlier chunks' keys) skips them: each wave sorts its keys in registers and three
+// merge rounds at most finish the run (6 barriers instead of 3 per radix pass).  Two-word
+// workgroups are held to 64 VGPRs, so that four of them (eight waves per SIMD) fit a CU.
 //
 // The running set's keys of the unit's range are looked up in the unit's hash table
 // before anything is sorted: a short range is streamed through the table (its first
@@ -1188,7 +1251,7 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
 // written, so the run handed to emit is disjoint from the set and the sort skips
 // every key the set already holds.
 template <int W>
-__global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(6, 8)))
+__global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(W == 2 ? 8 : 6, 8)))
 void bucket_kernel(BucketArgs a) {
     using C = DCfg<W>;
     constexpr int kBK = (C::CAP + kBThreads - 1) / kBThreads;  // keys per thread at capacity
@@ -1364,6 +1427,46 @@ void bucket_kernel(BucketArgs a) {
 #pragma unroll
         for (int ww = 0; ww < kBWaves; ++ww) u += s_u[ww];
 
+        if (u > 1 && u <= kBThreads) {  // workgroup-uniform
+            // one novel key per thread: thread t takes the t-th key of the waves' slices
+            int src = -1;
+            {
+                int pre = 0;
+#pragma unroll
+                for (int ww = 0; ww < kBWaves; ++ww) {
+                    const int c = s_u[ww];
+                    if (threadIdx.x >= pre && threadIdx.x < pre + c) src = ww * CHm + ((int)threadIdx.x - pre);
+                    pre += c;
+                }
+            }
+            const bool valid = src >= 0;
+            bool low_only = false;
+            if constexpr (W == 2) low_only = orx[1] == 0ull;  // every novel key has ref's top word
+            if (low_only) {
+                Key<1> *s_lw = reinterpret_cast<Key<1> *>(s_k0);
+                Key<1> lk;
+                lk.w[0] = valid ? s_k0[src].w[0] : 0ull;
+                __syncthreads();  // every source read before the 8-byte view is written
+                small_unit_sort<1>(lk, valid, u, s_lw);
+                for (int i = threadIdx.x; i < u; i += kBThreads) {
+                    Key<W> k = ref;
+                    k.w[0] = s_lw[i].w[0];
+                    store_key<W>(a.dst, start + i, k);
+                }
+            } else {
+                Key<W> k = ref;
+                if (valid) k = s_k0[src];
+                __syncthreads();  // every source read before buf is written
+                small_unit_sort<W>(k, valid, u, s_k0);
+                for (int i = threadIdx.x; i < u; i += kBThreads) store_key<W>(a.dst, start + i, s_k0[i]);
+            }
+            if (threadIdx.x == 0) {
+                a.nuniq[s] = u;
+                a.ucount[s] = u + nb;
+                a.ncount[s] = u;
+            }
+            return;
+        }
         // stable LSD radix sort of the u novel keys, in place in LDS.  The first pass
         // reads every wave's own slice (any starting order is fine); later passes
         // read the contiguous result of the previous pass.
