@@ -1014,8 +1014,9 @@ __device__ __forceinline__ void wave_scan256(const uint32_t tot[4], uint32_t pre
     }
 }
 
-// The bucket kernel runs 512-thread workgroups, three per CU (LDS and registers
-// allow that many), and the extra waves hide LDS and memory latency.
+// The bucket kernel runs 512-thread workgroups, three per CU for one-word keys and
+// four for two-word keys (what LDS allows), and the extra waves hide LDS and memory
+// latency.
 constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
 
@@ -1114,22 +1115,25 @@ __device__ __forceinline__ bool less_valid(const Key<W> &a, bool av, const Key<W
 template <int W>
 __device__ __forceinline__ void small_unit_sort(Key<W> key, bool valid, int u, Key<W> *buf) {
     const int lane = threadIdx.x & (kWave - 1);
+    // a wave holding no key (all of its positions at or above u) skips the network
+    if ((int)(threadIdx.x & ~(kWave - 1)) < u) {  // wave-uniform
 #pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
+        for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            Key<W> p;
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                Key<W> p;
 #pragma unroll
-            for (int q = 0; q < W; ++q) p.w[q] = __shfl_xor(key.w[q], j);
-            const bool pv = __shfl_xor((int)valid, j) != 0;
-            // ascending blocks of k lanes alternate with descending ones (the last is
-            // the whole wave, ascending); the lower lane of a pair keeps the smaller
-            // key of an ascending block
-            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
-            const bool take = keep_min ? less_valid<W>(p, pv, key, valid) : less_valid<W>(key, valid, p, pv);
-            if (take) {
-                key = p;
-                valid = pv;
+                for (int q = 0; q < W; ++q) p.w[q] = __shfl_xor(key.w[q], j);
+                const bool pv = __shfl_xor((int)valid, j) != 0;
+                // ascending blocks of k lanes alternate with descending ones (the last
+                // is the whole wave, ascending); the lower lane of a pair keeps the
+                // smaller key of an ascending block
+                const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+                const bool take = keep_min ? less_valid<W>(p, pv, key, valid) : less_valid<W>(key, valid, p, pv);
+                if (take) {
+                    key = p;
+                    valid = pv;
+                }
             }
         }
     }
