@@ -331,6 +331,34 @@ def test_dedup_shared_top_word_with_stragglers(n_straggle):
     _dedup_check(sci, cand, setin, 2)
 
 
+@pytest.mark.parametrize("W,shared_top", [(1, False), (2, False), (2, True)])
+@pytest.mark.parametrize("n_novel", [2, 3, 63, 64, 65, 127, 128, 129, 300, 511, 512, 513, 700])
+def test_dedup_single_unit_novel_counts(W, shared_top, n_novel):
+    """A dedup small enough to be one unit (the candidates fit the LDS capacity), so its
+    novel-key count is set exactly: counts on the edges of the register sort of small
+    units (64-key runs per wave, merge rounds, at most 512 keys) and just above it,
+    where the radix passes take over.  Each distinct key appears once or twice; 200
+    more distinct candidates are already in the set, which also holds 50 keys no
+    candidate has.  With shared_top every key has one top word (the low words are
+    sorted alone).  Union and novel keys against the oracle."""
+    sci = require_gpu()
+    rng = np.random.Generator(np.random.PCG64(1000 * W + 10 * n_novel + shared_top))
+    n_dist = n_novel + 250
+    keys = np.empty((0, W), np.uint64)
+    while keys.shape[0] < n_dist:  # distinct rows
+        more = rng.integers(0, 2**63, size=(2 * n_dist, W), dtype=np.int64).astype(np.uint64)
+        if shared_top:
+            more[:, 1] = np.uint64(0x00F0F0F0F0F0F0F0)
+        keys = np.unique(np.concatenate([keys, more]), axis=0)
+    keys = keys[rng.permutation(keys.shape[0])[:n_dist]]
+    cand_keys = keys[:n_novel + 200]  # the last 50 are set-only
+    cand = np.concatenate([cand_keys, cand_keys[::2]])
+    cand = cand[rng.permutation(cand.shape[0])]
+    setin = si.sort_keys(keys[n_novel:])
+    say(f"dedup one unit W={W} shared_top={shared_top} novel={n_novel} n={cand.shape[0]} set={setin.shape[0]}")
+    _dedup_check(sci, cand, setin, W)
+
+
 @pytest.mark.parametrize("name", ["tiny", "medium"])
 def test_dedup_of_generated_candidates(name):
     """Skewed real keys: coupled sets of a selected-set slice merged into the selected set."""
