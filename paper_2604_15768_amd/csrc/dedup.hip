@@ -1245,7 +1245,7 @@ __device__ __forceinline__ void finish_unit(const BucketArgs &a, int64_t s, cons
 // registers from before its first barrier, so it writes back into the buffer it read.
 // A unit left with at most one novel key per thread (most units once the set holds the
 // earlier chunks' keys) skips them: each wave sorts its keys in registers and three
-// merge rounds at most finish the run (6 barriers instead of 3 per radix pass).  Two-word
+// merge rounds at most finish the run (8 barriers at most instead of 3 per radix pass).  Two-word
 // workgroups are held to 64 VGPRs, so that four of them (eight waves per SIMD) fit a CU.
 //
 // The running set's keys of the unit's range are looked up in the unit's hash table
