@@ -1100,6 +1100,19 @@ __device__ __forceinline__ void unit_radix_pass(const Key<W> *cur, Key<W> *nxt, 
     __syncthreads();
 }
 
+// v of lane (this lane ^ j): j = 1 and 2 stay inside each group of four lanes and take a
+// DPP quad permutation (a vector move, no LDS round trip); wider strides a lane shuffle
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v, int j) {
+    if (j == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // lanes 1,0,3,2
+    if (j == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // lanes 2,3,0,1
+    return (uint32_t)__shfl_xor((int)v, j);
+}
+
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t v, int j) {
+    const uint32_t lo = lane_xor_u32((uint32_t)v, j), hi = lane_xor_u32((uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // a < b where an invalid key counts as larger than every valid one
 template <int W>
 __device__ __forceinline__ bool less_valid(const Key<W> &a, bool av, const Key<W> &b, bool bv) {
@@ -1108,7 +1121,7 @@ __device__ __forceinline__ bool less_valid(const Key<W> &a, bool av, const Key<W
 
 // Sort of at most one key per thread of a workgroup (u <= kBThreads distinct keys):
 // thread t holds key t (valid iff t < u).  Each wave sorts its 64 keys in registers
-// with a bitonic network (partners exchanged by lane shuffles, no barrier); the sorted
+// with a bitonic network (partners exchanged across lanes, no barrier); the sorted
 // runs of 64 are then merged pairwise in buf, each key moving to its index in its own
 // run plus its rank in the partner run (keys are distinct, so ranks never tie).  The
 // sorted keys end in buf[0, u).
@@ -1123,8 +1136,8 @@ __device__ __forceinline__ void small_unit_sort(Key<W> key, bool valid, int u, K
             for (int j = k >> 1; j > 0; j >>= 1) {
                 Key<W> p;
 #pragma unroll
-                for (int q = 0; q < W; ++q) p.w[q] = __shfl_xor(key.w[q], j);
-                const bool pv = __shfl_xor((int)valid, j) != 0;
+                for (int q = 0; q < W; ++q) p.w[q] = lane_xor_u64(key.w[q], j);
+                const bool pv = lane_xor_u32((uint32_t)valid, j) != 0u;
                 // ascending blocks of k lanes alternate with descending ones (the last
                 // is the whole wave, ascending); the lower lane of a pair keeps the
                 // smaller key of an ascending block
